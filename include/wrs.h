@@ -1,0 +1,190 @@
+/*
+ * wrs.h -- C ABI of an MI355X (gfx950) implementation of the data-parallel hot
+ * path of weighted random sampling from Huebschle-Schneider & Sanders,
+ * "Parallel Weighted Random Sampling" (arXiv 1903.00227).
+ *
+ * Problems (Section 1): items 0..n-1 with weights w_i >= 0, W = sum of w_i.
+ *   - alias table construction (Section 2.2 defines the table; Section 4.2 and
+ *     Algorithm 3 split the sweep of Section 4.1 into independent pieces);
+ *   - sampling with replacement (problem WRS-R): k independent alias queries;
+ *   - sampling without replacement (problem WRS-N) with exponential clocks
+ *     (Section 2.3): the k items with the smallest -ln(u_i)/w_i.
+ *
+ * Conventions for every call:
+ *   - Pointers named d_* are device pointers (HIP global memory of the current
+ *     device); h_* are host pointers.  The caller owns all of them; the library
+ *     never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous and ordered on that stream unless stated otherwise.
+ *   - Host-detectable errors are returned immediately and nothing is launched.
+ *     Errors found on the device (a weight that is negative, NaN or infinite, a
+ *     zero total) are written to a status word inside the caller's workspace and
+ *     read with wrs_status(); outputs are unspecified then.
+ *   - Items are 0-based; n is limited to 2^31 - 1 (indices are int32).
+ *   - Random bits come from Philox-4x32-10 (Salmon et al., SC'11), keyed by
+ *     `seed`; a draw is a pure function of (seed, stream_id, counter), so results
+ *     do not depend on launch shapes, batching or the order of calls.
+ */
+#ifndef WRS_H
+#define WRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One bucket of an alias table, 8 bytes, array-of-structs (the paper's
+ * experiments store tables this way, Section 10.1).  Bucket r returns item r
+ * with probability t and item `alias` otherwise (Section 2.2). */
+typedef struct {
+    float t;
+    int32_t alias;
+} wrs_entry;
+
+enum {
+    WRS_OK = 0,
+    WRS_EINVAL = -1,    /* null pointer, n < 1, n > 2^31-1, k < 0, workspace too small */
+    WRS_EDOMAIN = -2,   /* weight < 0, NaN or Inf; W == 0; WOR with k > #positive weights */
+    WRS_ENOMEM = -3,    /* an allocation inside the library failed (server only) */
+    WRS_EDEVICE = -4,   /* a HIP call failed; wrs_last_error() has the text */
+    WRS_EBUSY = -5,     /* server: request not finished / table in use */
+    WRS_ENOTFOUND = -6  /* server: unknown table or request id */
+};
+
+enum { WRS_OP_BUILD = 1, WRS_OP_WOR = 2 };
+
+/* Bytes of device workspace needed by wrs_alias_build (op = WRS_OP_BUILD, k
+ * ignored) or wrs_sample_wor (op = WRS_OP_WOR).  Depends on n (and k) only.
+ * Returns 0 for invalid arguments. */
+size_t wrs_workspace_bytes(int op, int64_t n, int64_t k);
+
+/* Build an alias table (Section 2.2) for d_w[0..n) into d_table[0..n).
+ * Method: the sweeping construction of Section 4.1 split into independent
+ * pieces as in Section 4.2 (Algorithm 3) with block-wise prefix sums
+ * (Section 4.2.2); all sums are exact integers on a grid derived from W, so
+ * the table equals the sequential sweep's table whenever every weight is at
+ * least 2^-40 of the mean weight (always for the paper's input families).
+ * d_w: n FP32 weights (device, any alignment).  d_table: n entries (device,
+ * 8-byte aligned).  d_ws: wrs_workspace_bytes(WRS_OP_BUILD, n, 0) bytes
+ * (device, 256-byte aligned).  The workspace afterwards holds the status word
+ * and the total weight (wrs_total_weight). */
+int wrs_alias_build(const float* d_w, int64_t n, wrs_entry* d_table,
+                    void* d_ws, size_t ws_bytes, void* stream);
+
+/* Draw k samples with replacement from a table: d_out[s] = query at counter
+ * c = first_counter + s, for s in [0, k).  One Philox block per draw with
+ * key = seed and counter = (c low 32 bits, c high 32 bits, stream_id, 0):
+ * bucket r = floor((x1 2^32 + x0) n / 2^64), coin u = (x2 >> 8) 2^-24, result
+ * r if u < t_r else alias_r (Section 2.2 query; branch-free select as in
+ * Section 10).  d_table: n entries with t in [0,1] and alias in [0,n) (the
+ * kernel trusts the table).  d_out: k int32 (device). */
+int wrs_alias_sample(const wrs_entry* d_table, int64_t n, uint64_t seed, uint32_t stream_id,
+                     uint64_t first_counter, int64_t k, int32_t* d_out, void* stream);
+
+/* Sample k distinct items without replacement (problem WRS-N, Section 1) by
+ * exponential clocks (Section 2.3): u_i = (x0 + 1) 2^-32 from Philox with
+ * counter (i low, i high, stream_id, 1), key_i = -ln(u_i) / w_i (FP64), and the
+ * k smallest keys, ties broken by the smaller index, win.  d_out receives the
+ * k indices in ascending order.  Requires 0 <= k and, on the device, k <= the
+ * number of positive weights (else status WRS_EDOMAIN).  d_ws:
+ * wrs_workspace_bytes(WRS_OP_WOR, n, k) bytes. */
+int wrs_sample_wor(const float* d_w, int64_t n, int64_t k, uint64_t seed, uint32_t stream_id,
+                   int32_t* d_out, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Synchronise `stream` and read the device status word of a workspace used by
+ * wrs_alias_build or wrs_sample_wor.  *status_out is WRS_OK or an error code. */
+int wrs_status(const void* d_ws, void* stream, int* status_out);
+
+/* Synchronise `stream` and read the total weight W found by the last
+ * wrs_alias_build on this workspace, as an unevaluated pair hi + lo. */
+int wrs_total_weight(const void* d_ws, void* stream, double* hi, double* lo);
+
+/* ---- batched operation -------------------------------------------------- */
+
+/* One independent table: build from d_w[0..n) into d_table, then draw k
+ * samples into d_out exactly as wrs_alias_sample(d_table, n, seed, stream_id,
+ * 0, k, d_out) would.  k may be 0 (build only). */
+typedef struct {
+    const float* d_w;
+    int64_t n;
+    wrs_entry* d_table;
+    int64_t k;
+    uint64_t seed;
+    uint32_t stream_id;
+    int32_t* d_out;
+} wrs_job;
+
+/* Workspace for a batch (device bytes); depends on the jobs' n only. */
+size_t wrs_batch_workspace_bytes(const wrs_job* h_jobs, int32_t njobs);
+
+/* Build and sample all jobs with one launch per phase for the whole batch
+ * (all tables share each launch).  Every job's table and samples are
+ * bit-identical to a single wrs_alias_build + wrs_alias_sample of that job.
+ * The descriptors are copied to the workspace, so h_jobs may be reused when
+ * the call returns.  The first call for a given batch shape records the
+ * launches into a hipGraph that later calls with identical descriptors replay
+ * (see wrs_batch_graph_mode). */
+int wrs_batch_build_sample(const wrs_job* h_jobs, int32_t njobs, void* d_ws, size_t ws_bytes,
+                           void* stream);
+
+/* Per-job status after a batch: synchronises `stream`, copies njobs status
+ * words into h_status. */
+int wrs_batch_status(const void* d_ws, int32_t njobs, void* stream, int* h_status);
+
+/* 1 (default): wrs_batch_build_sample records its launches once into a
+ * hipGraph per distinct batch (same descriptors and workspace) and replays it;
+ * 0: plain stream launches every call. */
+int wrs_batch_graph_mode(int enable);
+
+/* ---- serving -------------------------------------------------------------- */
+
+/* A request loop on one device: build requests create resident tables, sample
+ * requests draw from them.  Admission is limited by an HBM budget; admitted
+ * requests are packed into batched launches while earlier batches are still
+ * running (continuous batching), or issued one launch per request in arrival
+ * order when `one_at_a_time` is set (the baseline). */
+typedef struct {
+    size_t hbm_budget_bytes;   /* tables + per-request workspace, bytes */
+    int32_t max_batch;         /* requests per batched launch (>= 1) */
+    int32_t one_at_a_time;     /* 0: continuous batching, 1: one launch per request, FIFO */
+    int32_t inflight;          /* batches that may run concurrently (>= 1) */
+} wrs_serve_config;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t builds, samples;
+    uint64_t items_built, samples_drawn;
+    uint64_t launches;              /* batched launches issued */
+    double p50_us, p99_us, max_us;  /* completion - submission latency */
+    double busy_s;                  /* first submission to last completion */
+    size_t bytes_in_use, bytes_peak;
+    uint64_t tables_resident;
+} wrs_serve_stats_t;
+
+int wrs_serve_create(const wrs_serve_config* cfg, void** srv);
+/* Build request: d_w is a device pointer to n weights that must stay valid
+ * until the request completes.  *table_id names the resident table. */
+int wrs_serve_submit_build(void* srv, const float* d_w, int64_t n, uint64_t* table_id, uint64_t* req);
+/* Sample request: k draws from a resident table (seed, stream_id 0, counters
+ * 0..k-1) into the device buffer d_out (k int32).  The table may still be
+ * under construction; the request then runs after it. */
+int wrs_serve_submit_sample(void* srv, uint64_t table_id, int64_t k, uint64_t seed, int32_t* d_out,
+                            uint64_t* req);
+int wrs_serve_poll(void* srv, uint64_t req, int* done, int* status);
+int wrs_serve_wait(void* srv, uint64_t req, int* status);
+/* Drop a table once no pending request uses it (WRS_EBUSY otherwise). */
+int wrs_serve_release_table(void* srv, uint64_t table_id);
+/* Read a table back into host memory (n entries), e.g. to compare results. */
+int wrs_serve_read_table(void* srv, uint64_t table_id, wrs_entry* h_table, int64_t n);
+int wrs_serve_stats(void* srv, wrs_serve_stats_t* out);
+int wrs_serve_destroy(void* srv);
+
+/* Text of the last error on this thread ("" if none). */
+const char* wrs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WRS_H */

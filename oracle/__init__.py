@@ -50,6 +50,7 @@ def _load():
         "orc_vose_build": (ctypes.c_int, [P, i64, P, P]),
         "orc_sweep_build": (ctypes.c_int, [P, i64, P, P]),
         "orc_ratio_f32": (ctypes.c_float, [ctypes.c_float, u32, ctypes.c_float, u32]),
+        "orc_light_t_at": (ctypes.c_int, [P, i64, P, i64, P, P]),
         "orc_alias_sample": (ctypes.c_int, [P, P, i64, u64, u32, u64, i64, P]),
         "orc_alias_sample_at": (ctypes.c_int, [P, P, i64, u64, u32, P, i64, P]),
         "orc_reconstruct": (ctypes.c_int, [P, P, P, i64, P, P]),
@@ -116,6 +117,16 @@ def sweep_build(w):
 def ratio_f32(wa, ma, wb, mb) -> np.float32:
     """Correctly rounded FP32 value of (ma*wa)/(mb*wb) for FP32 wa, wb."""
     return np.float32(_load().orc_ratio_f32(float(np.float32(wa)), int(ma), float(np.float32(wb)), int(mb)))
+
+
+def light_t_at(w, idx):
+    """For each index: (is the item light, correctly rounded t = n w_i / W)."""
+    w = _f32(w)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    t = np.empty(idx.size, np.float32)
+    light = np.empty(idx.size, np.int32)
+    _check("orc_light_t_at", _load().orc_light_t_at(_ptr(w), w.size, _ptr(idx), idx.size, _ptr(t), _ptr(light)))
+    return light.astype(bool), t
 
 
 def alias_sample(t, alias, seed, stream_id, first_counter, k):

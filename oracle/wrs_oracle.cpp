@@ -399,6 +399,26 @@ extern "C" int orc_sweep_build(const float* w, int64_t n, float* t, int32_t* ali
     return ORC_OK;
 }
 
+/* Light buckets one by one (Section 2.2: a light item keeps its whole weight in
+   its own bucket, so t_i = n w_i / W): for each requested index, whether the
+   item is light (n w_i <= W) and the correctly rounded t_i. */
+extern "C" int orc_light_t_at(const float* w, int64_t n, const int64_t* idx, int64_t m, float* t_out,
+                              int32_t* is_light) {
+    if (!w || !idx || !t_out || !is_light || n < 1 || n > 2147483647LL || m < 0) return ORC_EINVAL;
+    if (!valid_weights(w, n)) return ORC_EDOMAIN;
+    xnum W;
+    exact_sum(w, n, &W);
+    if (x_is_zero(&W)) return ORC_EDOMAIN;
+    for (int64_t s = 0; s < m; ++s) {
+        if (idx[s] < 0 || idx[s] >= n) return ORC_EINVAL;
+        xnum v;
+        x_from_float_times(&v, w[idx[s]], (uint32_t)n);
+        is_light[s] = x_cmp(&v, &W) <= 0;
+        t_out[s] = x_ratio_to_f32(&v, &W);
+    }
+    return ORC_OK;
+}
+
 /* Correctly rounded FP32 of a/b for exact non-negative FP32-derived values:
    exposed for the tests of the rounding helper. a = wa*ma, b = wb*mb. */
 extern "C" float orc_ratio_f32(float wa, uint32_t ma, float wb, uint32_t mb) {

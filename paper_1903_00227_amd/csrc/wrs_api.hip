@@ -1,0 +1,321 @@
+// wrs_api.hip -- host side of the C ABI declared in include/wrs.h.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "wrs_internal.h"
+
+namespace wrs {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+static int dev_fail(const char* what, hipError_t e) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return WRS_EDEVICE;
+}
+
+static constexpr int64_t N_MAX = 2147483647LL;
+
+static void single_blocks(const JobDesc& J, int64_t blocks[PH_COUNT]) {
+    const int64_t C = J.ntiles;
+    blocks[PH_RED] = J.nred;
+    blocks[PH_FIN] = 1;
+    blocks[PH_TILE] = C;
+    blocks[PH_SEG] = J.nseg;
+    blocks[PH_TOP] = 1;
+    blocks[PH_PACK] = cdiv(2 * C, PACK_STEPS);
+    blocks[PH_SAMPLE] = cdiv(J.k, SAMPLES_PER_BLOCK);
+}
+
+}  // namespace wrs
+
+using namespace wrs;
+
+extern "C" const char* wrs_last_error(void) { return g_err; }
+
+extern "C" size_t wrs_workspace_bytes(int op, int64_t n, int64_t k) {
+    if (n < 1 || n > N_MAX || k < 0) return 0;
+    if (op == WRS_OP_BUILD) return build_ws_bytes(n);
+    if (op == WRS_OP_WOR) return wor_ws_bytes(n, k);
+    return 0;
+}
+
+extern "C" int wrs_alias_build(const float* d_w, int64_t n, wrs_entry* d_table, void* d_ws, size_t ws_bytes,
+                               void* stream) {
+    g_err[0] = 0;
+    if (!d_w || !d_table || !d_ws) { set_error("wrs_alias_build: null pointer"); return WRS_EINVAL; }
+    if (n < 1 || n > N_MAX) { set_error("wrs_alias_build: n = %lld out of [1, 2^31-1]", (long long)n); return WRS_EINVAL; }
+    if (ws_bytes < build_ws_bytes(n)) { set_error("wrs_alias_build: workspace %zu < %zu bytes", ws_bytes, build_ws_bytes(n)); return WRS_EINVAL; }
+    if (((uintptr_t)d_ws) & 255) { set_error("wrs_alias_build: workspace not 256-byte aligned"); return WRS_EINVAL; }
+    if (((uintptr_t)d_table) & 7) { set_error("wrs_alias_build: table not 8-byte aligned"); return WRS_EINVAL; }
+    JobTable jt;
+    memset(&jt, 0, sizeof jt);
+    JobDesc& J = jt.one;
+    J.w = d_w;
+    J.table = d_table;
+    build_ws_layout(J, d_ws, n);
+    int64_t blocks[PH_COUNT];
+    single_blocks(J, blocks);
+    hipError_t e = launch_build(jt, blocks, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail("wrs_alias_build launch", e);
+    return WRS_OK;
+}
+
+extern "C" int wrs_alias_sample(const wrs_entry* d_table, int64_t n, uint64_t seed, uint32_t stream_id,
+                                uint64_t first_counter, int64_t k, int32_t* d_out, void* stream) {
+    g_err[0] = 0;
+    if (!d_table || (k > 0 && !d_out)) { set_error("wrs_alias_sample: null pointer"); return WRS_EINVAL; }
+    if (n < 1 || n > N_MAX || k < 0) { set_error("wrs_alias_sample: bad n or k"); return WRS_EINVAL; }
+    if (((uintptr_t)d_table) & 7) { set_error("wrs_alias_sample: table not 8-byte aligned"); return WRS_EINVAL; }
+    if (k == 0) return WRS_OK;
+    if (cdiv(k, SAMPLES_PER_BLOCK) > 0x7fffffffLL) { set_error("wrs_alias_sample: k too large"); return WRS_EINVAL; }
+    JobTable jt;
+    memset(&jt, 0, sizeof jt);
+    JobDesc& J = jt.one;
+    J.table = const_cast<wrs_entry*>(d_table);
+    J.n = n;
+    J.k = k;
+    J.seed = seed;
+    J.stream_id = stream_id;
+    J.first_counter = first_counter;
+    J.out = d_out;
+    J.sc = nullptr;
+    hipError_t e = launch_sample(jt, cdiv(k, SAMPLES_PER_BLOCK), (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail("wrs_alias_sample launch", e);
+    return WRS_OK;
+}
+
+extern "C" int wrs_sample_wor(const float* d_w, int64_t n, int64_t k, uint64_t seed, uint32_t stream_id,
+                              int32_t* d_out, void* d_ws, size_t ws_bytes, void* stream) {
+    g_err[0] = 0;
+    if (!d_w || !d_ws || (k > 0 && !d_out)) { set_error("wrs_sample_wor: null pointer"); return WRS_EINVAL; }
+    if (n < 1 || n > N_MAX || k < 0) { set_error("wrs_sample_wor: bad n or k"); return WRS_EINVAL; }
+    if (k > n) { set_error("wrs_sample_wor: k > n"); return WRS_EDOMAIN; }
+    if (ws_bytes < wor_ws_bytes(n, k)) { set_error("wrs_sample_wor: workspace too small"); return WRS_EINVAL; }
+    if (((uintptr_t)d_ws) & 255) { set_error("wrs_sample_wor: workspace not 256-byte aligned"); return WRS_EINVAL; }
+    if (k == 0) {
+        // status word: OK
+        int ok = WRS_OK;
+        hipError_t e = hipMemcpyAsync((char*)d_ws + wor_status_offset(), &ok, sizeof ok, hipMemcpyHostToDevice,
+                                      (hipStream_t)stream);
+        if (e != hipSuccess) return dev_fail("wrs_sample_wor", e);
+        e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) return dev_fail("wrs_sample_wor", e);
+        return WRS_OK;
+    }
+    int rc = launch_wor(d_w, n, k, seed, stream_id, d_out, d_ws, (hipStream_t)stream);
+    if (rc != WRS_OK) return dev_fail("wrs_sample_wor launch", hipGetLastError());
+    return WRS_OK;
+}
+
+static int read_ws(const void* d_ws, size_t off, void* dst, size_t bytes, void* stream) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail("synchronize", e);
+    e = hipMemcpy(dst, (const char*)d_ws + off, bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_fail("read workspace", e);
+    return WRS_OK;
+}
+
+extern "C" int wrs_status(const void* d_ws, void* stream, int* status_out) {
+    g_err[0] = 0;
+    if (!d_ws || !status_out) { set_error("wrs_status: null pointer"); return WRS_EINVAL; }
+    // Both the build and the WOR workspaces start with their status word.
+    int s = 0;
+    int rc = read_ws(d_ws, 0, &s, sizeof s, stream);
+    if (rc) return rc;
+    *status_out = s;
+    return WRS_OK;
+}
+
+extern "C" int wrs_total_weight(const void* d_ws, void* stream, double* hi, double* lo) {
+    g_err[0] = 0;
+    if (!d_ws || !hi || !lo) { set_error("wrs_total_weight: null pointer"); return WRS_EINVAL; }
+    BuildScalars S;
+    int rc = read_ws(d_ws, 0, &S, sizeof S, stream);
+    if (rc) return rc;
+    *hi = S.W_hi;
+    *lo = S.W_lo;
+    return WRS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches.  Workspace: [JobDesc x njobs][offsets PH_COUNT x (njobs+1)]
+// [BuildScalars x njobs][per-job build workspaces].
+// ---------------------------------------------------------------------------
+namespace wrs {
+
+static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BatchHeader {
+    size_t jobs_off, off_off, sc_off, data_off, total;
+};
+
+static BatchHeader batch_header(int32_t njobs) {
+    BatchHeader h;
+    size_t o = 0;
+    h.jobs_off = o; o = a256(o + sizeof(JobDesc) * njobs);
+    h.off_off = o;  o = a256(o + sizeof(int64_t) * PH_COUNT * (njobs + 1));
+    h.sc_off = o;   o = a256(o + sizeof(BuildScalars) * njobs);
+    h.data_off = o;
+    h.total = o;
+    return h;
+}
+
+struct BatchPlan {
+    std::vector<char> key;           // descriptors + workspace address
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+static std::mutex g_batch_mu;
+static std::unordered_map<std::string, BatchPlan*> g_plans;
+static bool g_graph_mode = true;
+
+}  // namespace wrs
+
+extern "C" size_t wrs_batch_workspace_bytes(const wrs_job* h_jobs, int32_t njobs) {
+    if (!h_jobs || njobs < 1) return 0;
+    BatchHeader h = batch_header(njobs);
+    size_t total = h.data_off;
+    for (int32_t j = 0; j < njobs; ++j) {
+        if (h_jobs[j].n < 1 || h_jobs[j].n > N_MAX) return 0;
+        total += a256(build_ws_bytes(h_jobs[j].n));
+    }
+    return total;
+}
+
+extern "C" int wrs_batch_graph_mode(int enable) {
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    g_graph_mode = enable != 0;
+    return WRS_OK;
+}
+
+static int batch_record(const wrs_job* h_jobs, int32_t njobs, void* d_ws, hipStream_t st, JobTable& jt,
+                        int64_t* totals, std::vector<char>& host_blob) {
+    BatchHeader h = batch_header(njobs);
+    char* base = (char*)d_ws;
+    std::vector<JobDesc> descs(njobs);
+    std::vector<int64_t> off((size_t)PH_COUNT * (njobs + 1), 0);
+    size_t o = h.data_off;
+    for (int32_t j = 0; j < njobs; ++j) {
+        JobDesc& J = descs[j];
+        memset(&J, 0, sizeof J);
+        J.w = h_jobs[j].d_w;
+        J.table = h_jobs[j].d_table;
+        J.out = h_jobs[j].d_out;
+        J.k = h_jobs[j].k;
+        J.seed = h_jobs[j].seed;
+        J.stream_id = h_jobs[j].stream_id;
+        J.first_counter = 0;
+        build_ws_layout(J, base + o, h_jobs[j].n);
+        o += a256(build_ws_bytes(h_jobs[j].n));
+        J.sc = (BuildScalars*)(base + h.sc_off) + j;  // statuses side by side
+        int64_t b[PH_COUNT];
+        single_blocks(J, b);
+        for (int p = 0; p < PH_COUNT; ++p) off[(size_t)p * (njobs + 1) + j + 1] = off[(size_t)p * (njobs + 1) + j] + b[p];
+    }
+    for (int p = 0; p < PH_COUNT; ++p) totals[p] = off[(size_t)p * (njobs + 1) + njobs];
+    host_blob.assign(h.data_off, 0);
+    memcpy(host_blob.data() + h.jobs_off, descs.data(), sizeof(JobDesc) * njobs);
+    memcpy(host_blob.data() + h.off_off, off.data(), sizeof(int64_t) * off.size());
+    memset(&jt, 0, sizeof jt);
+    jt.jobs = (const JobDesc*)(base + h.jobs_off);
+    jt.off = (const int64_t*)(base + h.off_off);
+    jt.njobs = njobs;
+    (void)st;
+    return WRS_OK;
+}
+
+extern "C" int wrs_batch_build_sample(const wrs_job* h_jobs, int32_t njobs, void* d_ws, size_t ws_bytes,
+                                      void* stream) {
+    g_err[0] = 0;
+    if (!h_jobs || njobs < 1 || !d_ws) { set_error("wrs_batch_build_sample: bad arguments"); return WRS_EINVAL; }
+    if (((uintptr_t)d_ws) & 255) { set_error("wrs_batch_build_sample: workspace not 256-byte aligned"); return WRS_EINVAL; }
+    for (int32_t j = 0; j < njobs; ++j) {
+        const wrs_job& q = h_jobs[j];
+        if (!q.d_w || !q.d_table || q.n < 1 || q.n > N_MAX || q.k < 0 || (q.k > 0 && !q.d_out)) {
+            set_error("wrs_batch_build_sample: job %d invalid", j);
+            return WRS_EINVAL;
+        }
+        if (((uintptr_t)q.d_table) & 7) { set_error("wrs_batch_build_sample: job %d table misaligned", j); return WRS_EINVAL; }
+    }
+    const size_t need = wrs_batch_workspace_bytes(h_jobs, njobs);
+    if (ws_bytes < need) { set_error("wrs_batch_build_sample: workspace %zu < %zu", ws_bytes, need); return WRS_EINVAL; }
+    hipStream_t st = (hipStream_t)stream;
+    JobTable jt;
+    int64_t totals[PH_COUNT];
+    std::vector<char> blob;
+    batch_record(h_jobs, njobs, d_ws, st, jt, totals, blob);
+
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    std::string key((const char*)h_jobs, sizeof(wrs_job) * njobs);
+    key.append((const char*)&d_ws, sizeof d_ws);
+    if (g_graph_mode) {
+        auto it = g_plans.find(key);
+        if (it != g_plans.end()) {
+            hipError_t e = hipGraphLaunch(it->second->exec, st);
+            if (e != hipSuccess) return dev_fail("hipGraphLaunch", e);
+            return WRS_OK;
+        }
+    }
+    // Upload descriptors (synchronously: the host blob is temporary).
+    hipError_t e = hipMemcpyAsync(d_ws, blob.data(), blob.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return dev_fail("upload batch descriptors", e);
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return dev_fail("upload batch descriptors", e);
+    auto launch_all = [&]() -> hipError_t {
+        hipError_t r = launch_build(jt, totals, st);
+        if (r != hipSuccess) return r;
+        return launch_sample(jt, totals[PH_SAMPLE], st);
+    };
+    if (!g_graph_mode) {
+        e = launch_all();
+        if (e != hipSuccess) return dev_fail("batch launch", e);
+        return WRS_OK;
+    }
+    // Record on a library stream (the caller's may be the legacy default
+    // stream, which cannot be captured), replay on the caller's stream.
+    static hipStream_t cap = nullptr;
+    if (!cap) {
+        e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return dev_fail("create capture stream", e);
+    }
+    BatchPlan* plan = new BatchPlan();
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { delete plan; return dev_fail("hipStreamBeginCapture", e); }
+    const hipStream_t user_st = st;
+    st = cap;
+    hipError_t le = launch_all();
+    st = user_st;
+    e = hipStreamEndCapture(cap, &plan->graph);
+    if (le != hipSuccess || e != hipSuccess) { delete plan; return dev_fail("batch capture", le != hipSuccess ? le : e); }
+    e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(plan->graph); delete plan; return dev_fail("hipGraphInstantiate", e); }
+    g_plans[key] = plan;
+    e = hipGraphLaunch(plan->exec, st);
+    if (e != hipSuccess) return dev_fail("hipGraphLaunch", e);
+    return WRS_OK;
+}
+
+extern "C" int wrs_batch_status(const void* d_ws, int32_t njobs, void* stream, int* h_status) {
+    g_err[0] = 0;
+    if (!d_ws || njobs < 1 || !h_status) { set_error("wrs_batch_status: bad arguments"); return WRS_EINVAL; }
+    BatchHeader h = batch_header(njobs);
+    std::vector<BuildScalars> sc(njobs);
+    int rc = read_ws(d_ws, h.sc_off, sc.data(), sizeof(BuildScalars) * njobs, stream);
+    if (rc) return rc;
+    for (int32_t j = 0; j < njobs; ++j) h_status[j] = sc[j].status;
+    return WRS_OK;
+}

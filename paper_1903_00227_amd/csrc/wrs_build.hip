@@ -1,0 +1,812 @@
+// wrs_build.hip -- alias-table construction and sampling kernels for gfx950.
+//
+// Construction follows the sweeping algorithm of Section 4.1 (Algorithm 2),
+// split into independent pieces as in Section 4.2 (Algorithm 3) with the
+// block-wise prefix sums of Section 4.2.2.  Everything is n-scaled: item i has
+// size n*w_i and every bucket holds W.  The sweep is a stable merge of the
+// light items, keyed by the deficit of the lights before them, with the heavy
+// items, keyed by their own cumulative excess (a heavy goes first on ties):
+//   D(i) = sum over the first i lights of (W - n w),  A_i = D(i-1),
+//   E(j) = sum over the first j heavies of (n w - W), B_j = E(j).
+// Light i keeps t = n w_i / W and takes the next heavy not yet emitted as its
+// alias; heavy j keeps t = 1 + (E(j) - D(I)) / W where I lights precede it and
+// takes the next heavy as its alias.  The paper's split() finds such merge
+// states by binary search over prefix sums; here the prefix sums are exact
+// integers on the grid 2^G (see quantize), so every block decides every
+// comparison identically and the merge can be cut anywhere.
+//
+// Phases (one launch each, all jobs of a batch share every launch):
+//   k_reduce    W as a double-double, weight domain check
+//   k_finalize  grid exponent G and integer capacity Q = round(W / 2^G)
+//   k_tileagg   per tile of 1024 items: #lights, light deficit, heavy excess
+//   k_scan_*    exclusive prefix over tiles (segmented)
+//   k_pack      merge, cut at tile events, each block emitting 16 events
+//   k_sample    alias queries
+#include <float.h>
+#include <math.h>
+#include <stdio.h>
+
+#include "wrs_device.h"
+
+namespace wrs {
+
+static constexpr int32_t FH_NONE = 0x7fffffff;
+
+// ---------------------------------------------------------------------------
+// Workspace layout of one table.
+// ---------------------------------------------------------------------------
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BuildLayout {
+    size_t sc, red, redinfo, NL, DP, EP, FH, sNL, sDP, sEP, sFH, total;
+};
+
+static BuildLayout layout_for(int64_t n) {
+    const int64_t C = cdiv(n, TILE);
+    const int64_t R = cdiv(n, RED_CHUNK);
+    const int64_t S = cdiv(C, SCAN_SEG);
+    BuildLayout L;
+    size_t o = 0;
+    L.sc = o;      o = align256(o + sizeof(BuildScalars));
+    L.red = o;     o = align256(o + sizeof(double2) * R);
+    L.redinfo = o; o = align256(o + sizeof(uint32_t) * 2 * R);
+    L.NL = o;      o = align256(o + sizeof(uint32_t) * (C + 1));
+    L.DP = o;      o = align256(o + sizeof(u128) * (C + 1));
+    L.EP = o;      o = align256(o + sizeof(u128) * (C + 1));
+    L.FH = o;      o = align256(o + sizeof(int32_t) * (C + 1));
+    L.sNL = o;     o = align256(o + sizeof(uint32_t) * (S + 1));
+    L.sDP = o;     o = align256(o + sizeof(u128) * (S + 1));
+    L.sEP = o;     o = align256(o + sizeof(u128) * (S + 1));
+    L.sFH = o;     o = align256(o + sizeof(int32_t) * (S + 1));
+    L.total = o;
+    return L;
+}
+
+size_t build_ws_bytes(int64_t n) { return layout_for(n).total; }
+
+void build_ws_layout(JobDesc& J, void* ws, int64_t n) {
+    const BuildLayout L = layout_for(n);
+    char* b = (char*)ws;
+    J.n = n;
+    J.ntiles = (int32_t)cdiv(n, TILE);
+    J.nred = (int32_t)cdiv(n, RED_CHUNK);
+    J.nseg = (int32_t)cdiv(J.ntiles, SCAN_SEG);
+    J.sc = (BuildScalars*)(b + L.sc);
+    J.red = (double2*)(b + L.red);
+    J.redinfo = (uint32_t*)(b + L.redinfo);
+    J.NL = (uint32_t*)(b + L.NL);
+    J.DP = (u128*)(b + L.DP);
+    J.EP = (u128*)(b + L.EP);
+    J.FH = (int32_t*)(b + L.FH);
+    J.sNL = (uint32_t*)(b + L.sNL);
+    J.sDP = (u128*)(b + L.sDP);
+    J.sEP = (u128*)(b + L.sEP);
+    J.sFH = (int32_t*)(b + L.sFH);
+}
+
+// ---------------------------------------------------------------------------
+// a1: total weight (double-double) and domain check, RED_CHUNK items per block.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void red_item(float v, double& hi, double& lo, uint32_t& bad, uint32_t& pos) {
+    bad |= (uint32_t)(!(v >= 0.0f) || isinf(v));
+    pos += (uint32_t)(v > 0.0f);
+    dd_acc(hi, lo, (double)v);
+}
+
+__device__ __forceinline__ void block_reduce_dd(double& hi, double& lo, uint32_t& bad, uint32_t& pos,
+                                                double* s_hi, double* s_lo, uint32_t* s_bad, uint32_t* s_pos) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double oh = __shfl_xor(hi, off, 64);
+        const double ol = __shfl_xor(lo, off, 64);
+        bad |= __shfl_xor(bad, off, 64);
+        pos += __shfl_xor(pos, off, 64);
+        dd_add(hi, lo, oh, ol);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_hi[wv] = hi;
+        s_lo[wv] = lo;
+        s_bad[wv] = bad;
+        s_pos[wv] = pos;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        hi = s_hi[0];
+        lo = s_lo[0];
+        bad = s_bad[0];
+        pos = s_pos[0];
+        for (int k = 1; k < TPB / 64; ++k) {
+            dd_add(hi, lo, s_hi[k], s_lo[k]);
+            bad |= s_bad[k];
+            pos += s_pos[k];
+        }
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_reduce(JobTable jt) {
+    __shared__ int s_job;
+    __shared__ double s_hi[TPB / 64], s_lo[TPB / 64];
+    __shared__ uint32_t s_bad[TPB / 64], s_pos[TPB / 64];
+    int64_t lb;
+    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    const int64_t base = lb * RED_CHUNK;
+    const int64_t end = min(base + (int64_t)RED_CHUNK, J.n);
+    const float* w = J.w;
+    double hi = 0.0, lo = 0.0;
+    uint32_t bad = 0, pos = 0;
+    if ((((uintptr_t)(w + base)) & 15) == 0) {
+        const int64_t nv = (end - base) >> 2;
+        const float4* w4 = (const float4*)(w + base);
+        for (int64_t g = threadIdx.x; g < nv; g += TPB) {
+            const float4 v = w4[g];
+            red_item(v.x, hi, lo, bad, pos);
+            red_item(v.y, hi, lo, bad, pos);
+            red_item(v.z, hi, lo, bad, pos);
+            red_item(v.w, hi, lo, bad, pos);
+        }
+        for (int64_t i = base + 4 * nv + threadIdx.x; i < end; i += TPB) red_item(w[i], hi, lo, bad, pos);
+    } else {
+        for (int64_t i = base + threadIdx.x; i < end; i += TPB) red_item(w[i], hi, lo, bad, pos);
+    }
+    block_reduce_dd(hi, lo, bad, pos, s_hi, s_lo, s_bad, s_pos);
+    if (threadIdx.x == 0) {
+        J.red[lb] = make_double2(hi, lo);
+        J.redinfo[2 * lb] = bad;
+        J.redinfo[2 * lb + 1] = pos;
+    }
+}
+
+__device__ __forceinline__ u128 u128_from_integral_double(double d) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(d);
+    const int e = (int)((bits >> 52) & 0x7FF) - 1075;
+    const uint64_t m = (bits & ((1ull << 52) - 1)) | (1ull << 52);
+    return e >= 0 ? ((u128)m << e) : (u128)(m >> (-e));
+}
+
+// a1 (second half): combine partials in a fixed order, derive the grid.
+__global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
+    __shared__ int s_job;
+    __shared__ double s_hi[TPB / 64], s_lo[TPB / 64];
+    __shared__ uint32_t s_bad[TPB / 64], s_pos[TPB / 64];
+    int64_t lb;
+    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    double hi = 0.0, lo = 0.0;
+    uint32_t bad = 0, pos = 0;
+    for (int r = threadIdx.x; r < J.nred; r += TPB) {
+        const double2 p = J.red[r];
+        dd_add(hi, lo, p.x, p.y);
+        bad |= J.redinfo[2 * r];
+        pos += J.redinfo[2 * r + 1];
+    }
+    block_reduce_dd(hi, lo, bad, pos, s_hi, s_lo, s_bad, s_pos);
+    if (threadIdx.x != 0) return;
+    BuildScalars S;
+    S.status = WRS_OK;
+    S.npos = pos;
+    const double s = hi + lo;
+    lo = lo - (s - hi);
+    hi = s;
+    S.W_hi = hi;
+    S.W_lo = lo;
+    S.G = 0;
+    S.Q = 0;
+    S.Qd = 0;
+    S.rQ = 0;
+    S.nscale = 0;
+    S.Qn = 0;
+    if (bad || !(hi > 0.0)) {
+        S.status = WRS_EDOMAIN;
+    } else {
+        const int64_t n = J.n;
+        int e;
+        frexp(hi, &e);                               // hi in [2^(e-1), 2^e)
+        const int lgn = 63 - __clzll((long long)n);  // floor(log2 n)
+        const int G = (e - 1) - lgn - 62;            // W / 2^G in [2^(lgn+62), 2^(lgn+63))
+        const double Qh = ldexp(hi, -G);             // integral (>= 2^62 with 53 bits)
+        const double Ql = rint(ldexp(lo, -G));
+        u128 Q = u128_from_integral_double(Qh);
+        Q = (u128)((i128)Q + (i128)(int64_t)Ql);
+        S.G = G;
+        S.Q = Q;
+        S.Qd = u128_to_double(Q);
+        S.rQ = 1.0 / S.Qd;
+        S.nscale = ldexp((double)n, -G);
+        // floor(Q / n) without 128-bit division: estimate, then correct.
+        uint64_t qn = (uint64_t)(S.Qd / (double)n);
+        const i128 rem = (i128)Q - (i128)n * (i128)qn;
+        qn = (uint64_t)((int64_t)qn + (int64_t)(rem / (i128)n));
+        while ((u128)n * (u128)(qn + 1) <= Q) ++qn;
+        while ((u128)n * (u128)qn > Q) --qn;
+        S.Qn = qn;
+    }
+    *J.sc = S;
+}
+
+// ---------------------------------------------------------------------------
+// a2: per-tile aggregates.  Item i is light iff n q_i <= Q, i.e. q_i <= Qn.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void load_tile_items(const float* w, int64_t base, int cnt, float v[IPT]) {
+    const int i0 = threadIdx.x * IPT;
+    if (i0 + IPT <= cnt && ((((uintptr_t)(w + base + i0)) & 15) == 0)) {
+        const float4 x = *(const float4*)(w + base + i0);
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < IPT; ++e) v[e] = (i0 + e < cnt) ? w[base + i0 + e] : 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
+    __shared__ int s_job;
+    __shared__ ScanTmp tmp;
+    __shared__ int s_fh;
+    int64_t lb;
+    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    const BuildScalars* sc = J.sc;
+    if (sc->status != WRS_OK) return;
+    const int G = sc->G;
+    const uint64_t Qn = sc->Qn;
+    const u128 Q = sc->Q;
+    const int64_t n = J.n;
+    const int64_t c = lb;
+    const int64_t base = c * TILE;
+    const int cnt = (int)min((int64_t)TILE, n - base);
+    if (threadIdx.x == 0) s_fh = FH_NONE;
+    float v[IPT];
+    load_tile_items(J.w, base, cnt, v);
+    uint32_t nl = 0;
+    u128 sql = 0, sqh = 0;
+    int fh = FH_NONE;
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const int i = threadIdx.x * IPT + e;
+        if (i < cnt) {
+            const u128 q = quantize(v[e], G);
+            if (q <= (u128)Qn) {
+                ++nl;
+                sql += q;
+            } else {
+                sqh += q;
+                fh = min(fh, (int)(base + i));
+            }
+        }
+    }
+    __syncthreads();
+    if (fh != FH_NONE) atomicMin(&s_fh, fh);
+    uint32_t nl_ex, nl_tot;
+    u128 a_ex, b_ex, a_tot, b_tot;
+    block_scan3(nl, sql, sqh, nl_ex, a_ex, b_ex, nl_tot, a_tot, b_tot, tmp);
+    if (threadIdx.x == 0) {
+        const uint32_t nh = (uint32_t)cnt - nl_tot;
+        const u128 D = (u128)nl_tot * Q - (u128)n * a_tot;
+        const u128 E = (u128)n * b_tot - (u128)nh * Q;
+        J.NL[c] = nl_tot;
+        J.DP[c] = D;
+        J.EP[c] = E;
+        J.FH[c] = s_fh;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a3: exclusive prefix over tiles (NL, DP, EP) and "first heavy at or after"
+// (FH), in segments of SCAN_SEG tiles, then over segments, then fixed up.
+// ---------------------------------------------------------------------------
+constexpr int SEG_PER_THREAD = SCAN_SEG / TPB;
+
+__device__ __forceinline__ int block_suffix_min_excl(int v, int* s_w) {
+    // minimum of v over threads with a larger index
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_down(incl, d, 64);
+        if (lane + d < 64) incl = min(incl, o);
+    }
+    if (lane == 0) s_w[wv] = incl;
+    __syncthreads();
+    int later = FH_NONE;
+    for (int k = wv + 1; k < TPB / 64; ++k) later = min(later, s_w[k]);
+    const int nxt = __shfl_down(incl, 1, 64);
+    const int excl_in_wave = (lane == 63) ? FH_NONE : nxt;
+    __syncthreads();
+    return min(excl_in_wave, later);
+}
+
+__global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
+    __shared__ int s_job;
+    __shared__ ScanTmp tmp;
+    __shared__ int s_w[TPB / 64];
+    int64_t lb;
+    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    if (J.sc->status != WRS_OK) return;
+    const int64_t C = J.ntiles;
+    const int64_t t0 = lb * SCAN_SEG + (int64_t)threadIdx.x * SEG_PER_THREAD;
+    uint32_t nl[SEG_PER_THREAD];
+    u128 dp[SEG_PER_THREAD], ep[SEG_PER_THREAD];
+    int fh[SEG_PER_THREAD];
+    uint32_t snl = 0;
+    u128 sdp = 0, sep = 0;
+    int fmin = FH_NONE;
+#pragma unroll
+    for (int e = 0; e < SEG_PER_THREAD; ++e) {
+        const int64_t c = t0 + e;
+        if (c < C) {
+            nl[e] = J.NL[c];
+            dp[e] = J.DP[c];
+            ep[e] = J.EP[c];
+            fh[e] = J.FH[c];
+        } else {
+            nl[e] = 0;
+            dp[e] = 0;
+            ep[e] = 0;
+            fh[e] = FH_NONE;
+        }
+        snl += nl[e];
+        sdp += dp[e];
+        sep += ep[e];
+        fmin = min(fmin, fh[e]);
+    }
+    uint32_t nl_ex, nl_tot;
+    u128 dp_ex, ep_ex, dp_tot, ep_tot;
+    block_scan3(snl, sdp, sep, nl_ex, dp_ex, ep_ex, nl_tot, dp_tot, ep_tot, tmp);
+    const int later = block_suffix_min_excl(fmin, s_w);
+    int suf = later;
+#pragma unroll
+    for (int e = SEG_PER_THREAD - 1; e >= 0; --e) {
+        suf = min(suf, fh[e]);
+        fh[e] = suf;
+    }
+#pragma unroll
+    for (int e = 0; e < SEG_PER_THREAD; ++e) {
+        const int64_t c = t0 + e;
+        if (c < C) {
+            J.NL[c] = nl_ex;
+            J.DP[c] = dp_ex;
+            J.EP[c] = ep_ex;
+            J.FH[c] = fh[e];
+        }
+        nl_ex += nl[e];
+        dp_ex += dp[e];
+        ep_ex += ep[e];
+    }
+    if (threadIdx.x == 0) {
+        J.sNL[lb] = nl_tot;
+        J.sDP[lb] = dp_tot;
+        J.sEP[lb] = ep_tot;
+        J.sFH[lb] = min(fmin, later);  // thread 0 holds the first tiles: the segment minimum
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_scan_top(JobTable jt) {
+    __shared__ int s_job;
+    __shared__ ScanTmp tmp;
+    __shared__ int s_w[TPB / 64];
+    int64_t lb;
+    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    if (J.sc->status != WRS_OK) return;
+    const int S = J.nseg;
+    const int per = (S + TPB - 1) / TPB;   // segments per thread (<= 4 for n < 2^31)
+    const int s0 = threadIdx.x * per;
+    uint32_t snl = 0;
+    u128 sdp = 0, sep = 0;
+    int fmin = FH_NONE;
+    for (int e = 0; e < per; ++e) {
+        const int s = s0 + e;
+        if (s < S) {
+            snl += J.sNL[s];
+            sdp += J.sDP[s];
+            sep += J.sEP[s];
+            fmin = min(fmin, J.sFH[s]);
+        }
+    }
+    uint32_t nl_ex, nl_tot;
+    u128 dp_ex, ep_ex, dp_tot, ep_tot;
+    block_scan3(snl, sdp, sep, nl_ex, dp_ex, ep_ex, nl_tot, dp_tot, ep_tot, tmp);
+    const int later = block_suffix_min_excl(fmin, s_w);
+    // suffix minimum, inclusive, over this thread's segments
+    int fsuf[4];
+    int suf = later;
+    for (int e = per - 1; e >= 0; --e) {
+        const int s = s0 + e;
+        if (s < S) suf = min(suf, J.sFH[s]);
+        if (e < 4) fsuf[e] = suf;
+    }
+    __syncthreads();
+    for (int e = 0; e < per; ++e) {
+        const int s = s0 + e;
+        if (s < S) {
+            const uint32_t a = J.sNL[s];
+            const u128 b = J.sDP[s], c = J.sEP[s];
+            J.sNL[s] = nl_ex;
+            J.sDP[s] = dp_ex;
+            J.sEP[s] = ep_ex;
+            J.sFH[s] = fsuf[e];
+            nl_ex += a;
+            dp_ex += b;
+            ep_ex += c;
+        }
+    }
+    if (threadIdx.x == 0) {
+        const int64_t C = J.ntiles;
+        J.NL[C] = nl_tot;
+        J.DP[C] = dp_tot;
+        J.EP[C] = ep_tot;
+        J.FH[C] = FH_NONE;
+        J.sFH[S] = FH_NONE;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_scan_fix(JobTable jt) {
+    __shared__ int s_job;
+    int64_t lb;
+    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    if (J.sc->status != WRS_OK) return;
+    const int64_t C = J.ntiles;
+    const uint32_t pnl = J.sNL[lb];
+    const u128 pdp = J.sDP[lb], pep = J.sEP[lb];
+    const int nxt = J.sFH[lb + 1];
+    for (int e = 0; e < SEG_PER_THREAD; ++e) {
+        const int64_t c = lb * SCAN_SEG + (int64_t)e * TPB + threadIdx.x;
+        if (c < C) {
+            J.NL[c] += pnl;
+            J.DP[c] += pdp;
+            J.EP[c] += pep;
+            const int f = J.FH[c];
+            J.FH[c] = (f != FH_NONE) ? f : nxt;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a4 + a5: split and pack.
+//
+// Tile events: light event x (x = 1..C) is the merge state just before the
+// first light of tile x (key DP[x]; the last one, x = C, comes after every
+// heavy); heavy event y (y = 1..C) is the state just after the last heavy of
+// tile y-1 (key EP[y]).  Heavy event y precedes light event x iff
+// EP[y] <= DP[x].  The 2C events in merge order cut the sweep into cells; in
+// each cell the lights come from one tile and the heavies from one tile.  Block
+// b handles events [16 b, 16 b + 16): it finds its start by a merge-path search
+// over (DP, EP), refines the exact state inside the two current tiles, then
+// merges cell by cell.
+// ---------------------------------------------------------------------------
+struct TileSlot {
+    u128 key[TILE];     // lights [0, nl): D before the light; heavies [nl, nl+nh): E through the heavy
+    int32_t idx[TILE];  // item index
+    float tl[TILE];     // t of the lights
+    int32_t nl, nh;
+};
+
+struct PackShared {
+    TileSlot slot[2];
+    ScanTmp tmp;
+    int s_job;
+    int s_best;
+};
+
+// Fill slot S with tile c (c == C gives an empty tile).
+__device__ void load_pack_tile(TileSlot& S, int64_t c, const JobDesc& J, const BuildScalars& sc,
+                               ScanTmp& tmp) {
+    const int64_t C = J.ntiles;
+    if (c >= C) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            S.nl = 0;
+            S.nh = 0;
+        }
+        __syncthreads();
+        return;
+    }
+    const int64_t n = J.n;
+    const int64_t base = c * TILE;
+    const int cnt = (int)min((int64_t)TILE, n - base);
+    const u128 Q = sc.Q;
+    const uint64_t Qn = sc.Qn;
+    const u128 Dbase = J.DP[c];
+    const u128 Ebase = J.EP[c];
+    float v[IPT];
+    load_tile_items(J.w, base, cnt, v);
+    u128 q[IPT];
+    bool light[IPT];
+    uint32_t nl = 0;
+    u128 dsum = 0, esum = 0;
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const int i = threadIdx.x * IPT + e;
+        q[e] = quantize(v[e], sc.G);
+        light[e] = (i < cnt) && (q[e] <= (u128)Qn);
+        if (i < cnt) {
+            if (light[e]) {
+                ++nl;
+                dsum += Q - (u128)n * q[e];
+            } else {
+                esum += (u128)n * q[e] - Q;
+            }
+        }
+    }
+    uint32_t nl_ex, nl_tot;
+    u128 d_ex, e_ex, d_tot, e_tot;
+    __syncthreads();  // the slot may still be read by the previous cell
+    block_scan3(nl, dsum, esum, nl_ex, d_ex, e_ex, nl_tot, d_tot, e_tot, tmp);
+    uint32_t lr = nl_ex;
+    uint32_t hr = (uint32_t)(threadIdx.x * IPT) - nl_ex;  // heavies before this thread's items
+    u128 dacc = Dbase + d_ex;
+    u128 eacc = Ebase + e_ex;
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const int i = threadIdx.x * IPT + e;
+        if (i < cnt) {
+            if (light[e]) {
+                S.key[lr] = dacc;
+                S.idx[lr] = (int32_t)(base + i);
+                S.tl[lr] = (float)((double)v[e] * sc.nscale * sc.rQ);
+                dacc += Q - (u128)n * q[e];
+                ++lr;
+            } else {
+                eacc += (u128)n * q[e] - Q;
+                const int p = (int)nl_tot + (int)hr;
+                S.key[p] = eacc;
+                S.idx[p] = (int32_t)(base + i);
+                ++hr;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        S.nl = (int)nl_tot;
+        S.nh = cnt - (int)nl_tot;
+    }
+    __syncthreads();
+}
+
+// number of lights at positions [from, nl) of S with key < v, plus from
+__device__ __forceinline__ int lights_below(const TileSlot& S, int from, u128 v) {
+    int lo = from, hi = S.nl;  // first position with key >= v
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (S.key[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// number of heavies at positions [from, nh) of S with key <= v, plus from
+__device__ __forceinline__ int heavies_upto(const TileSlot& S, int from, u128 v) {
+    int lo = from, hi = S.nh;  // first position with key > v
+    const int off = S.nl;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (S.key[off + mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void store_entry(wrs_entry* table, int32_t item, float t, int32_t alias) {
+    uint2 v = make_uint2(__float_as_uint(t), (uint32_t)alias);
+    *(uint2*)(table + item) = v;
+}
+
+__global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
+    __shared__ PackShared sh;
+    int64_t lb;
+    const JobDesc& J = job_of_block(jt, lb, &sh.s_job);
+    if (J.sc->status != WRS_OK) return;
+    const BuildScalars sc = *J.sc;
+    const int64_t C = J.ntiles;
+    const int64_t total = 2 * C;
+    const int64_t s0 = lb * PACK_STEPS;
+    const int64_t s1 = min(s0 + (int64_t)PACK_STEPS, total);
+    const u128* DP = J.DP;
+    const u128* EP = J.EP;
+    // Light event x precedes heavy event s0 - x + 1 (none if beyond C).  The
+    // last light event (x = C) has key +infinity.
+    auto dpkey_lt = [&](int64_t x, const u128& v) -> bool {  // DPkey(x) < v
+        return x < C && DP[x] < v;
+    };
+    auto pred = [&](int64_t x) -> bool {
+        const int64_t y1 = s0 - x + 1;
+        return x == 0 || y1 > C || dpkey_lt(x, EP[y1]);
+    };
+    // k-ary search for the largest x in [lo, hi] with pred(x); pred(lo) holds.
+    int64_t lo = max((int64_t)0, s0 - C), hi = min(s0, C);
+    while (lo < hi) {
+        const int64_t len = hi - lo;
+        const int64_t stride = (len + TPB - 1) / TPB;
+        if (threadIdx.x == 0) sh.s_best = -1;
+        __syncthreads();
+        const int64_t xt = lo + (int64_t)(threadIdx.x + 1) * stride;
+        if (xt <= hi && pred(xt)) atomicMax(&sh.s_best, (int)threadIdx.x);
+        __syncthreads();
+        const int best = sh.s_best;
+        __syncthreads();
+        const int64_t nlo = (best >= 0) ? lo + (int64_t)(best + 1) * stride : lo;
+        const int64_t nhi = min(hi, nlo + stride - 1);
+        lo = nlo;
+        hi = nhi;
+    }
+    int64_t x = lo, y = s0 - lo;
+    int sa = 0, sb = 0;
+    load_pack_tile(sh.slot[0], x, J, sc, sh.tmp);
+    if (y != x) {
+        sb = 1;
+        load_pack_tile(sh.slot[1], y, J, sc, sh.tmp);
+    }
+    int pl = 0, ph = 0;
+    if (s0 > 0) {
+        const bool last_light = x >= 1 && (y == 0 || !(dpkey_lt(x, EP[y]) ));
+        // last_light <=> EP[y] <= DPkey(x)
+        if (last_light) {
+            ph = (x < C) ? heavies_upto(sh.slot[sb], 0, DP[x]) : 0;
+        } else {
+            pl = lights_below(sh.slot[sa], 0, EP[y]);
+        }
+    }
+    const u128 Q = sc.Q;
+    for (int64_t s = s0; s < s1; ++s) {
+        TileSlot& A = sh.slot[sa];
+        TileSlot& B = sh.slot[sb];
+        const bool has_h = y + 1 <= C;
+        const bool has_l = x + 1 <= C;
+        const u128 EPn = has_h ? EP[y + 1] : (u128)0;
+        const bool heavy_ev = has_h && (!has_l || !dpkey_lt(x + 1, EPn));
+        const int nlx = A.nl, nhy = B.nh, offB = B.nl;
+        int nlc, nhc;
+        if (heavy_ev) {
+            nhc = nhy - ph;
+            nlc = lights_below(A, pl, EPn) - pl;
+        } else {
+            nlc = nlx - pl;
+            nhc = (y < C) ? heavies_upto(B, ph, DP[x + 1]) - ph : 0;
+        }
+        const int32_t nextH = (y + 1 <= C) ? J.FH[y + 1] : FH_NONE;
+        const u128 Dend = DP[min(x + 1, C)];
+        const int m = nlc + nhc;
+        if (m > 0) {
+            const int d0 = (int)(((int64_t)m * threadIdx.x) / TPB);
+            const int d1 = (int)(((int64_t)m * (threadIdx.x + 1)) / TPB);
+            if (d1 > d0) {
+                // merge path: largest j in [max(0,d0-nlc), min(d0,nhc)] with
+                // j == 0 or d0-j >= nlc or Bkey[j-1] <= Akey[d0-j]
+                int jlo = max(0, d0 - nlc), jhi = min(d0, nhc);
+                while (jlo < jhi) {
+                    const int mid = (jlo + jhi + 1) >> 1;
+                    const bool ok = (d0 - mid >= nlc) || (B.key[offB + ph + mid - 1] <= A.key[pl + d0 - mid]);
+                    if (ok) jlo = mid; else jhi = mid - 1;
+                }
+                int j = jlo, i = d0 - jlo;
+                for (int d = d0; d < d1; ++d) {
+                    const bool take_h = (j < nhc) && (i >= nlc || B.key[offB + ph + j] <= A.key[pl + i]);
+                    if (take_h) {
+                        const int hp = offB + ph + j;
+                        const u128 E = B.key[hp];
+                        const u128 Dn = (pl + i < nlx) ? A.key[pl + i] : Dend;
+                        const i128 num = (i128)Q + (i128)E - (i128)Dn;
+                        float t = (float)(u128_to_double((u128)(num > 0 ? num : 0)) * sc.rQ);
+                        t = fminf(t, 1.0f);
+                        const int32_t own = B.idx[hp];
+                        const int32_t al = (ph + j + 1 < nhy) ? B.idx[hp + 1] : (nextH != FH_NONE ? nextH : own);
+                        store_entry(J.table, own, t, al);
+                        ++j;
+                    } else {
+                        const int lp = pl + i;
+                        const int32_t own = A.idx[lp];
+                        float t = A.tl[lp];
+                        int32_t al;
+                        if (ph + j < nhy) {
+                            al = B.idx[offB + ph + j];
+                        } else if (nextH != FH_NONE) {
+                            al = nextH;
+                        } else {
+                            al = own;
+                            t = fminf(t, 1.0f);
+                        }
+                        store_entry(J.table, own, t, al);
+                        ++i;
+                    }
+                }
+            }
+        }
+        pl += nlc;
+        ph += nhc;
+        if (heavy_ev) {
+            ++y;
+            ph = 0;
+            if (y == x) {
+                sb = sa;
+            } else {
+                sb = 1 - sa;
+                load_pack_tile(sh.slot[sb], y, J, sc, sh.tmp);
+            }
+        } else {
+            ++x;
+            pl = 0;
+            if (x == y) {
+                sa = sb;
+            } else {
+                sa = 1 - sb;
+                load_pack_tile(sh.slot[sa], x, J, sc, sh.tmp);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a6: alias queries (Section 2.2 query; select without a branch as in Section 10).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
+    __shared__ int s_job;
+    int64_t lb;
+    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    if (J.sc != nullptr && J.sc->status != WRS_OK) return;
+    const int64_t k = J.k;
+    const uint64_t n = (uint64_t)J.n;
+    const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
+    const uint64_t* table = (const uint64_t*)J.table;
+    const int64_t s0 = lb * SAMPLES_PER_BLOCK + threadIdx.x;
+    uint32_t r[SAMPLE_UNROLL];
+    float u[SAMPLE_UNROLL];
+#pragma unroll
+    for (int e = 0; e < SAMPLE_UNROLL; ++e) {
+        const int64_t s = s0 + (int64_t)e * SAMPLE_TPB;
+        const uint64_t c = J.first_counter + (uint64_t)s;
+        const uint4 x = philox4x32_10(make_uint4((uint32_t)c, (uint32_t)(c >> 32), J.stream_id, 0u), k0, k1);
+        // floor((x1 2^32 + x0) n / 2^64) for n < 2^31
+        const uint64_t lo = ((uint64_t)x.x * n) >> 32;
+        const uint64_t hi = (uint64_t)x.y * n + lo;
+        r[e] = (uint32_t)(hi >> 32);
+        u[e] = (float)(x.z >> 8) * (1.0f / 16777216.0f);
+    }
+    uint64_t ent[SAMPLE_UNROLL];
+#pragma unroll
+    for (int e = 0; e < SAMPLE_UNROLL; ++e) {
+        const int64_t s = s0 + (int64_t)e * SAMPLE_TPB;
+        ent[e] = (s < k) ? __builtin_nontemporal_load(table + r[e]) : 0ull;
+    }
+#pragma unroll
+    for (int e = 0; e < SAMPLE_UNROLL; ++e) {
+        const int64_t s = s0 + (int64_t)e * SAMPLE_TPB;
+        if (s < k) {
+            const float t = __uint_as_float((uint32_t)ent[e]);
+            const int32_t a = (int32_t)(uint32_t)(ent[e] >> 32);
+            J.out[s] = (u[e] < t) ? (int32_t)r[e] : a;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_build(const JobTable& jt0, const int64_t* blocks, hipStream_t st) {
+    JobTable jt = jt0;
+#define WRS_LAUNCH(kern, ph)                                                       \
+    do {                                                                           \
+        if (blocks[ph] > 0) {                                                      \
+            jt.phase = ph;                                                         \
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks[ph]), dim3(TPB), 0, st, jt); \
+            hipError_t e_ = hipGetLastError();                                     \
+            if (e_ != hipSuccess) return e_;                                       \
+        }                                                                          \
+    } while (0)
+    WRS_LAUNCH(k_reduce, PH_RED);
+    WRS_LAUNCH(k_finalize, PH_FIN);
+    WRS_LAUNCH(k_tileagg, PH_TILE);
+    WRS_LAUNCH(k_scan_seg, PH_SEG);
+    WRS_LAUNCH(k_scan_top, PH_TOP);
+    WRS_LAUNCH(k_scan_fix, PH_SEG);
+    WRS_LAUNCH(k_pack, PH_PACK);
+#undef WRS_LAUNCH
+    return hipSuccess;
+}
+
+hipError_t launch_sample(const JobTable& jt0, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    JobTable jt = jt0;
+    jt.phase = PH_SAMPLE;
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)blocks), dim3(SAMPLE_TPB), 0, st, jt);
+    return hipGetLastError();
+}
+
+}  // namespace wrs

@@ -1,0 +1,97 @@
+// wrs_internal.h -- shared definitions of the HIP library (kernels + host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wrs.h"
+
+namespace wrs {
+
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+// Launch geometry.  Every size below is a constant, so a table's result depends
+// on its own n only (never on how jobs are batched).
+constexpr int TILE = 1024;          // items per tile (classification and prefix sums)
+constexpr int TPB = 256;            // threads per block of the tile kernels
+constexpr int IPT = TILE / TPB;     // items per thread in a tile
+constexpr int PACK_STEPS = 16;      // coarse tile events per pack block
+constexpr int RED_CHUNK = 65536;    // items per block of the total-weight reduction
+constexpr int SCAN_SEG = 2048;      // tiles per segment of the tile scan
+constexpr int SAMPLE_TPB = 256;     // threads per block of the sampler
+constexpr int SAMPLE_UNROLL = 8;    // draws per thread of the sampler
+constexpr int SAMPLES_PER_BLOCK = SAMPLE_TPB * SAMPLE_UNROLL;
+
+// Per-table scalars written by the reduction, read by every later phase.
+struct alignas(16) BuildScalars {
+    int32_t status;   // WRS_OK or an error code (first word of every workspace)
+    int32_t G;        // grid exponent
+    int32_t pad[2];
+    u128 Q;           // n-scaled bucket capacity on the grid 2^G: round(W / 2^G)
+    double W_hi, W_lo;
+    double Qd;        // Q as double
+    double rQ;        // 1 / Qd
+    double nscale;    // n * 2^-G
+    uint64_t Qn;      // floor(Q / n): item i is light iff q_i <= Qn
+    int64_t npos;     // number of positive weights
+};
+
+// Everything one table needs on the device.
+struct JobDesc {
+    const float* w;
+    wrs_entry* table;
+    int32_t* out;
+    int64_t n;
+    int64_t k;
+    uint64_t seed;
+    uint64_t first_counter;
+    uint32_t stream_id;
+    int32_t ntiles;       // C = ceil(n / TILE)
+    int32_t nred;         // ceil(n / RED_CHUNK)
+    int32_t nseg;         // ceil(C / SCAN_SEG)
+    BuildScalars* sc;
+    double2* red;         // [nred] partial sums (hi, lo)
+    uint32_t* redinfo;    // [2 * nred] bad-value flag, positive count
+    uint32_t* NL;         // [C+1] lights before tile c
+    u128* DP;             // [C+1] light deficit before tile c
+    u128* EP;             // [C+1] heavy excess before tile c
+    int32_t* FH;          // [C+1] first heavy item in tiles >= c, -1 if none
+    uint32_t* sNL;        // [nseg+1] segment totals / prefixes of the tile scan
+    u128* sDP;
+    u128* sEP;
+    int32_t* sFH;
+};
+
+enum Phase { PH_RED = 0, PH_FIN, PH_TILE, PH_SEG, PH_TOP, PH_PACK, PH_SAMPLE, PH_COUNT };
+
+// A launch covers one phase of one job (jobs == nullptr, description in `one`)
+// or of many jobs (device array `jobs`, with block offsets per phase in
+// off[phase * (njobs + 1) + j]).
+struct JobTable {
+    const JobDesc* jobs;
+    const int64_t* off;
+    int32_t njobs;
+    int32_t phase;
+    JobDesc one;
+};
+
+// Byte size of the per-table workspace and the pointer layout inside it.
+size_t build_ws_bytes(int64_t n);
+void build_ws_layout(JobDesc& J, void* ws, int64_t n);
+
+// Host launchers (stream-ordered).
+hipError_t launch_build(const JobTable& jt, const int64_t* blocks, hipStream_t st);
+hipError_t launch_sample(const JobTable& jt, int64_t blocks, hipStream_t st);
+
+// WOR
+size_t wor_ws_bytes(int64_t n, int64_t k);
+int launch_wor(const float* w, int64_t n, int64_t k, uint64_t seed, uint32_t sid, int32_t* out,
+               void* ws, hipStream_t st);
+int wor_status_offset();
+
+// Error reporting for the C ABI.
+void set_error(const char* fmt, ...);
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace wrs

@@ -1,0 +1,577 @@
+// wrs_serve.hip -- a request loop on one device (the wrs_serve_* C ABI).
+//
+// Build requests create resident alias tables; sample requests draw from them.
+// A scheduler thread admits requests in arrival order while they fit an HBM
+// budget (one device pool carved by a first-fit allocator, so no hipMalloc on
+// the request path), packs admitted requests into batched launches (all builds
+// of a tick share one launch per phase, all samples share one sampler launch),
+// and keeps up to `inflight` such batches running on separate streams while it
+// forms the next (continuous batching).  With one_at_a_time = 1 the same loop
+// issues one request per launch, strictly in arrival order, as the baseline.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "wrs_internal.h"
+
+namespace wrs {
+
+static double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over one device allocation.
+class Pool {
+   public:
+    bool init(size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (hipMalloc(&base_, bytes) != hipSuccess) return false;
+        size_ = bytes;
+        free_[0] = bytes;
+        return true;
+    }
+    ~Pool() {
+        if (base_) (void)hipFree(base_);
+    }
+    void* alloc(size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, sz = it->second;
+                free_.erase(it);
+                if (sz > bytes) free_[off + bytes] = sz - bytes;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return (char*)base_ + off;
+            }
+        }
+        return nullptr;
+    }
+    void release(void* p, size_t bytes) {
+        if (!p) return;
+        bytes = (bytes + 255) & ~(size_t)255;
+        size_t off = (char*)p - (char*)base_;
+        used_ -= bytes;
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + bytes == nx->first) {
+            bytes += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += bytes;
+                return;
+            }
+        }
+        free_[off] = bytes;
+    }
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+    size_t size() const { return size_; }
+
+   private:
+    void* base_ = nullptr;
+    size_t size_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;
+};
+
+enum { OP_BUILD = 1, OP_SAMPLE = 2 };
+enum TableState { T_QUEUED, T_BUILDING, T_READY, T_FAILED };
+
+struct Table {
+    uint64_t id;
+    int64_t n;
+    const float* d_w;
+    wrs_entry* d_table = nullptr;
+    size_t table_bytes = 0;
+    TableState state = T_QUEUED;
+    hipEvent_t ready = nullptr;  // recorded after the build launch
+    int refs = 0;                // queued or running requests using the table
+    int status = WRS_OK;
+    BuildScalars* sc = nullptr;  // status word of the build (pool memory)
+    uint64_t last_use = 0;
+};
+
+struct Request {
+    uint64_t id;
+    int op;
+    uint64_t table_id;
+    int64_t k = 0;
+    uint64_t seed = 0;
+    int32_t* d_out = nullptr;
+    double t_submit = 0, t_done = 0;
+    int status = WRS_OK;
+    bool done = false;
+};
+
+struct Batch {
+    int slot;
+    hipEvent_t ev;
+    std::vector<Request*> reqs;
+    std::vector<std::pair<void*, size_t>> scratch;  // pool memory to give back
+};
+
+struct Server {
+    wrs_serve_config cfg;
+    int device = 0;
+    Pool pool;
+    std::mutex mu;
+    std::condition_variable cv, cv_done;
+    std::deque<Request*> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+    std::unordered_map<uint64_t, std::unique_ptr<Table>> tables;
+    std::vector<hipStream_t> streams;
+    std::vector<char*> staging;  // pinned host buffers for descriptors, one per slot
+    std::vector<size_t> staging_bytes;
+    std::vector<bool> slot_busy;
+    std::deque<Batch> running;
+    std::thread worker;
+    bool stop = false;
+    uint64_t next_id = 1;
+    uint64_t clock = 0;
+    // statistics
+    uint64_t submitted = 0, completed = 0, failed = 0, builds = 0, samples = 0, items = 0, drawn = 0, launches = 0;
+    double t_first = -1, t_last = 0;
+    std::vector<double> lat_us;
+};
+
+static size_t descriptor_bytes(int njobs) {
+    size_t o = 0;
+    o = (o + sizeof(JobDesc) * njobs + 255) & ~(size_t)255;
+    o = (o + sizeof(int64_t) * PH_COUNT * (njobs + 1) + 255) & ~(size_t)255;
+    return o;
+}
+
+static void finish_request(Server& S, Request* r, int status, double t) {
+    r->status = status;
+    r->done = true;
+    r->t_done = t;
+    S.completed++;
+    if (status != WRS_OK) S.failed++;
+    S.lat_us.push_back((t - r->t_submit) * 1e6);
+    S.t_last = std::max(S.t_last, t);
+    auto it = S.tables.find(r->table_id);
+    if (it != S.tables.end()) it->second->refs--;
+}
+
+// Retire finished batches (called with the lock held).
+static void retire(Server& S, bool block) {
+    while (!S.running.empty()) {
+        Batch& b = S.running.front();
+        hipError_t q = block ? hipEventSynchronize(b.ev) : hipEventQuery(b.ev);
+        if (q == hipErrorNotReady) break;
+        const double t = now_s();
+        // read build statuses from the device for the tables built in this batch
+        for (Request* r : b.reqs) {
+            auto it = S.tables.find(r->table_id);
+            Table* tb = (it != S.tables.end()) ? it->second.get() : nullptr;
+            int st = (q == hipSuccess) ? WRS_OK : WRS_EDEVICE;
+            if (r->op == OP_BUILD && tb) {
+                if (st == WRS_OK) {
+                    int32_t dev_status = WRS_OK;
+                    if (hipMemcpy(&dev_status, &tb->sc->status, sizeof dev_status, hipMemcpyDeviceToHost) != hipSuccess)
+                        dev_status = WRS_EDEVICE;
+                    st = dev_status;
+                }
+                tb->state = (st == WRS_OK) ? T_READY : T_FAILED;
+                tb->status = st;
+            }
+            if (r->op == OP_SAMPLE && tb && tb->status != WRS_OK) st = tb->status;
+            finish_request(S, r, st, t);
+        }
+        for (auto& p : b.scratch) S.pool.release(p.first, p.second);
+        (void)hipEventDestroy(b.ev);
+        S.slot_busy[b.slot] = false;
+        S.running.pop_front();
+        S.cv_done.notify_all();
+    }
+}
+
+// Drop least recently used idle tables until `need` bytes fit (lock held).
+static bool make_room(Server& S, size_t need) {
+    while (S.pool.used() + need > S.cfg.hbm_budget_bytes) {
+        Table* victim = nullptr;
+        for (auto& kv : S.tables) {
+            Table* t = kv.second.get();
+            if (t->refs == 0 && (t->state == T_READY || t->state == T_FAILED) &&
+                (!victim || t->last_use < victim->last_use))
+                victim = t;
+        }
+        if (!victim) return false;
+        S.pool.release(victim->d_table, victim->table_bytes);
+        S.pool.release(victim->sc, 256);
+        if (victim->ready) (void)hipEventDestroy(victim->ready);
+        S.tables.erase(victim->id);
+    }
+    return true;
+}
+
+// Form and launch one batch on a free slot (lock held).  Returns false if
+// nothing could be issued.
+static bool issue(Server& S) {
+    int slot = -1;
+    for (int i = 0; i < (int)S.slot_busy.size(); ++i)
+        if (!S.slot_busy[i]) { slot = i; break; }
+    if (slot < 0 || S.queue.empty()) return false;
+    const int maxb = S.cfg.one_at_a_time ? 1 : std::max(1, S.cfg.max_batch);
+    std::vector<Request*> take;
+    std::vector<Request*> bld, smp;
+    std::vector<std::pair<void*, size_t>> scratch;
+    while (!S.queue.empty() && (int)take.size() < maxb) {
+        Request* r = S.queue.front();
+        Table* tb = S.tables[r->table_id].get();
+        if (r->op == OP_BUILD) {
+            const size_t wsb = build_ws_bytes(tb->n) + 256;
+            const size_t need = tb->table_bytes + wsb + 256;
+            if (!make_room(S, need)) break;  // wait for memory (FIFO: no overtaking)
+            tb->d_table = (wrs_entry*)S.pool.alloc(tb->table_bytes);
+            void* ws = S.pool.alloc(wsb);
+            tb->sc = (BuildScalars*)S.pool.alloc(256);
+            if (!tb->d_table || !ws || !tb->sc) {  // fragmentation: undo and wait
+                S.pool.release(tb->d_table, tb->table_bytes);
+                S.pool.release(ws, wsb);
+                S.pool.release(tb->sc, 256);
+                tb->d_table = nullptr;
+                tb->sc = nullptr;
+                break;
+            }
+            scratch.push_back({ws, wsb});
+            tb->state = T_BUILDING;
+            bld.push_back(r);
+        } else {
+            if (tb->state == T_FAILED) {
+                S.queue.pop_front();
+                finish_request(S, r, tb->status, now_s());
+                continue;
+            }
+            smp.push_back(r);
+        }
+        tb->last_use = ++S.clock;
+        take.push_back(r);
+        S.queue.pop_front();
+    }
+    if (take.empty()) return false;
+    hipStream_t st = S.streams[slot];
+    // descriptors: builds first, then samples, each its own job table
+    const int nb = (int)bld.size(), ns = (int)smp.size();
+    const size_t bb = nb ? descriptor_bytes(nb) : 0, sb = ns ? descriptor_bytes(ns) : 0;
+    const size_t need_stage = bb + sb;
+    if (S.staging_bytes[slot] < need_stage) {
+        if (S.staging[slot]) (void)hipHostFree(S.staging[slot]);
+        S.staging[slot] = nullptr;
+        if (hipHostMalloc((void**)&S.staging[slot], need_stage) != hipSuccess) S.staging[slot] = nullptr;
+        S.staging_bytes[slot] = S.staging[slot] ? need_stage : 0;
+    }
+    char* dev_desc = (char*)S.pool.alloc(need_stage);
+    if (dev_desc) scratch.push_back({dev_desc, need_stage});
+    bool ok = S.staging[slot] && dev_desc;
+    // samples wait for tables built by batches still running on other streams
+    for (Request* r : smp) {
+        Table* tb = S.tables[r->table_id].get();
+        bool same = false;
+        for (Request* q : bld) same |= (q->table_id == r->table_id);
+        if (!same && tb->ready && tb->state == T_BUILDING) (void)hipStreamWaitEvent(st, tb->ready, 0);
+    }
+    if (ok && nb) {
+        std::vector<JobDesc> d(nb);
+        std::vector<int64_t> off((size_t)PH_COUNT * (nb + 1), 0);
+        size_t wsi = 0;
+        for (int j = 0; j < nb; ++j) {
+            Table* tb = S.tables[bld[j]->table_id].get();
+            memset(&d[j], 0, sizeof(JobDesc));
+            d[j].w = tb->d_w;
+            d[j].table = tb->d_table;
+            d[j].k = 0;
+            build_ws_layout(d[j], scratch[wsi++].first, tb->n);
+            d[j].sc = tb->sc;
+            int64_t b[PH_COUNT] = {d[j].nred, 1, d[j].ntiles, d[j].nseg, 1, cdiv(2 * (int64_t)d[j].ntiles, PACK_STEPS), 0};
+            for (int p = 0; p < PH_COUNT; ++p) off[(size_t)p * (nb + 1) + j + 1] = off[(size_t)p * (nb + 1) + j] + b[p];
+        }
+        char* h = S.staging[slot];
+        const size_t o_off = (sizeof(JobDesc) * nb + 255) & ~(size_t)255;
+        memcpy(h, d.data(), sizeof(JobDesc) * nb);
+        memcpy(h + o_off, off.data(), sizeof(int64_t) * off.size());
+        ok = hipMemcpyAsync(dev_desc, h, bb, hipMemcpyHostToDevice, st) == hipSuccess;
+        JobTable jt;
+        memset(&jt, 0, sizeof jt);
+        jt.jobs = (const JobDesc*)dev_desc;
+        jt.off = (const int64_t*)(dev_desc + o_off);
+        jt.njobs = nb;
+        int64_t totals[PH_COUNT];
+        for (int p = 0; p < PH_COUNT; ++p) totals[p] = off[(size_t)p * (nb + 1) + nb];
+        ok = ok && launch_build(jt, totals, st) == hipSuccess;
+        S.launches++;
+        for (int j = 0; j < nb; ++j) {
+            Table* tb = S.tables[bld[j]->table_id].get();
+            if (!tb->ready) (void)hipEventCreateWithFlags(&tb->ready, hipEventDisableTiming);
+            (void)hipEventRecord(tb->ready, st);
+        }
+    }
+    if (ok && ns) {
+        std::vector<JobDesc> d(ns);
+        std::vector<int64_t> off((size_t)PH_COUNT * (ns + 1), 0);
+        for (int j = 0; j < ns; ++j) {
+            Table* tb = S.tables[smp[j]->table_id].get();
+            memset(&d[j], 0, sizeof(JobDesc));
+            d[j].table = tb->d_table;
+            d[j].n = tb->n;
+            d[j].k = smp[j]->k;
+            d[j].seed = smp[j]->seed;
+            d[j].stream_id = 0;
+            d[j].out = smp[j]->d_out;
+            d[j].sc = tb->sc;  // skips the draws if the build failed
+            off[(size_t)PH_SAMPLE * (ns + 1) + j + 1] = off[(size_t)PH_SAMPLE * (ns + 1) + j] + cdiv(smp[j]->k, SAMPLES_PER_BLOCK);
+        }
+        char* h = S.staging[slot] + bb;
+        const size_t o_off = (sizeof(JobDesc) * ns + 255) & ~(size_t)255;
+        memcpy(h, d.data(), sizeof(JobDesc) * ns);
+        memcpy(h + o_off, off.data(), sizeof(int64_t) * off.size());
+        ok = ok && hipMemcpyAsync(dev_desc + bb, h, sb, hipMemcpyHostToDevice, st) == hipSuccess;
+        JobTable jt;
+        memset(&jt, 0, sizeof jt);
+        jt.jobs = (const JobDesc*)(dev_desc + bb);
+        jt.off = (const int64_t*)(dev_desc + bb + o_off);
+        jt.njobs = ns;
+        ok = ok && launch_sample(jt, off[(size_t)PH_SAMPLE * (ns + 1) + ns], st) == hipSuccess;
+        S.launches++;
+    }
+    Batch b;
+    b.slot = slot;
+    b.reqs = take;
+    b.scratch = scratch;
+    (void)hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+    (void)hipEventRecord(b.ev, st);
+    if (!ok) {
+        set_error("wrs_serve: batch launch failed");
+        (void)hipStreamSynchronize(st);
+    }
+    S.slot_busy[slot] = true;
+    S.running.push_back(b);
+    return true;
+}
+
+static void worker_main(Server* S) {
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (true) {
+        retire(*S, false);
+        bool issued = false;
+        while (issue(*S)) issued = true;
+        if (S->stop && S->queue.empty() && S->running.empty()) break;
+        if (!issued) {
+            if (S->running.empty()) {
+                S->cv.wait_for(lk, std::chrono::milliseconds(50));
+            } else {
+                // poll the oldest batch; short sleeps keep the completion times sharp
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            }
+        }
+    }
+}
+
+}  // namespace wrs
+
+using namespace wrs;
+
+extern "C" int wrs_serve_create(const wrs_serve_config* cfg, void** srv) {
+    if (!cfg || !srv || cfg->hbm_budget_bytes < (1u << 20)) { set_error("wrs_serve_create: bad config"); return WRS_EINVAL; }
+    auto* S = new Server();
+    S->cfg = *cfg;
+    if (S->cfg.max_batch < 1) S->cfg.max_batch = 1;
+    if (S->cfg.inflight < 1) S->cfg.inflight = 1;
+    if (S->cfg.one_at_a_time) S->cfg.inflight = 1;
+    (void)hipGetDevice(&S->device);
+    if (!S->pool.init(cfg->hbm_budget_bytes)) {
+        delete S;
+        set_error("wrs_serve_create: cannot reserve %zu bytes", cfg->hbm_budget_bytes);
+        return WRS_ENOMEM;
+    }
+    for (int i = 0; i < S->cfg.inflight; ++i) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            delete S;
+            set_error("wrs_serve_create: stream creation failed");
+            return WRS_EDEVICE;
+        }
+        S->streams.push_back(st);
+        S->staging.push_back(nullptr);
+        S->staging_bytes.push_back(0);
+        S->slot_busy.push_back(false);
+    }
+    S->worker = std::thread(worker_main, S);
+    *srv = S;
+    return WRS_OK;
+}
+
+extern "C" int wrs_serve_submit_build(void* srv, const float* d_w, int64_t n, uint64_t* table_id, uint64_t* req) {
+    auto* S = (Server*)srv;
+    if (!S || !d_w || !table_id || !req || n < 1 || n > 2147483647LL) { set_error("wrs_serve_submit_build: bad arguments"); return WRS_EINVAL; }
+    const size_t need = (size_t)n * sizeof(wrs_entry) + build_ws_bytes(n) + 1024;
+    if (need > S->cfg.hbm_budget_bytes) { set_error("wrs_serve_submit_build: request exceeds the HBM budget"); return WRS_ENOMEM; }
+    std::lock_guard<std::mutex> g(S->mu);
+    auto t = std::make_unique<Table>();
+    t->id = S->next_id++;
+    t->n = n;
+    t->d_w = d_w;
+    t->table_bytes = (size_t)n * sizeof(wrs_entry);
+    t->refs = 1;
+    auto r = std::make_unique<Request>();
+    r->id = S->next_id++;
+    r->op = OP_BUILD;
+    r->table_id = t->id;
+    r->t_submit = now_s();
+    if (S->t_first < 0) S->t_first = r->t_submit;
+    *table_id = t->id;
+    *req = r->id;
+    S->queue.push_back(r.get());
+    S->tables[t->id] = std::move(t);
+    S->reqs[r->id] = std::move(r);
+    S->submitted++;
+    S->builds++;
+    S->items += (uint64_t)n;
+    S->cv.notify_one();
+    return WRS_OK;
+}
+
+extern "C" int wrs_serve_submit_sample(void* srv, uint64_t table_id, int64_t k, uint64_t seed, int32_t* d_out,
+                                       uint64_t* req) {
+    auto* S = (Server*)srv;
+    if (!S || !req || k < 1 || !d_out) { set_error("wrs_serve_submit_sample: bad arguments"); return WRS_EINVAL; }
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->tables.find(table_id);
+    if (it == S->tables.end()) { set_error("wrs_serve_submit_sample: unknown table %llu", (unsigned long long)table_id); return WRS_ENOTFOUND; }
+    it->second->refs++;
+    auto r = std::make_unique<Request>();
+    r->id = S->next_id++;
+    r->op = OP_SAMPLE;
+    r->table_id = table_id;
+    r->k = k;
+    r->seed = seed;
+    r->d_out = d_out;
+    r->t_submit = now_s();
+    if (S->t_first < 0) S->t_first = r->t_submit;
+    *req = r->id;
+    S->queue.push_back(r.get());
+    S->reqs[r->id] = std::move(r);
+    S->submitted++;
+    S->samples++;
+    S->drawn += (uint64_t)k;
+    S->cv.notify_one();
+    return WRS_OK;
+}
+
+extern "C" int wrs_serve_poll(void* srv, uint64_t req, int* done, int* status) {
+    auto* S = (Server*)srv;
+    if (!S || !done || !status) return WRS_EINVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(req);
+    if (it == S->reqs.end()) return WRS_ENOTFOUND;
+    *done = it->second->done;
+    *status = it->second->status;
+    return WRS_OK;
+}
+
+extern "C" int wrs_serve_wait(void* srv, uint64_t req, int* status) {
+    auto* S = (Server*)srv;
+    if (!S || !status) return WRS_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(req);
+    if (it == S->reqs.end()) return WRS_ENOTFOUND;
+    Request* r = it->second.get();
+    S->cv_done.wait(lk, [&] { return r->done; });
+    *status = r->status;
+    return WRS_OK;
+}
+
+extern "C" int wrs_serve_release_table(void* srv, uint64_t table_id) {
+    auto* S = (Server*)srv;
+    if (!S) return WRS_EINVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->tables.find(table_id);
+    if (it == S->tables.end()) return WRS_ENOTFOUND;
+    Table* t = it->second.get();
+    if (t->refs > 0 || t->state == T_QUEUED || t->state == T_BUILDING) return WRS_EBUSY;
+    S->pool.release(t->d_table, t->table_bytes);
+    S->pool.release(t->sc, 256);
+    if (t->ready) (void)hipEventDestroy(t->ready);
+    S->tables.erase(it);
+    return WRS_OK;
+}
+
+extern "C" int wrs_serve_read_table(void* srv, uint64_t table_id, wrs_entry* h_table, int64_t n) {
+    auto* S = (Server*)srv;
+    if (!S || !h_table) return WRS_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->tables.find(table_id);
+    if (it == S->tables.end()) return WRS_ENOTFOUND;
+    Table* t = it->second.get();
+    if (n != t->n) return WRS_EINVAL;
+    S->cv_done.wait(lk, [&] { return t->state == T_READY || t->state == T_FAILED; });
+    if (t->state == T_FAILED) return t->status;
+    if (hipMemcpy(h_table, t->d_table, t->table_bytes, hipMemcpyDeviceToHost) != hipSuccess) return WRS_EDEVICE;
+    return WRS_OK;
+}
+
+extern "C" int wrs_serve_stats(void* srv, wrs_serve_stats_t* out) {
+    auto* S = (Server*)srv;
+    if (!S || !out) return WRS_EINVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    memset(out, 0, sizeof *out);
+    out->submitted = S->submitted;
+    out->completed = S->completed;
+    out->failed = S->failed;
+    out->builds = S->builds;
+    out->samples = S->samples;
+    out->items_built = S->items;
+    out->samples_drawn = S->drawn;
+    out->launches = S->launches;
+    if (!S->lat_us.empty()) {
+        std::vector<double> v = S->lat_us;
+        auto q = [&](double p) {
+            size_t i = (size_t)(p * (v.size() - 1) + 0.5);
+            std::nth_element(v.begin(), v.begin() + i, v.end());
+            return v[i];
+        };
+        out->p50_us = q(0.50);
+        out->p99_us = q(0.99);
+        out->max_us = *std::max_element(v.begin(), v.end());
+    }
+    out->busy_s = (S->t_first >= 0) ? S->t_last - S->t_first : 0.0;
+    out->bytes_in_use = S->pool.used();
+    out->bytes_peak = S->pool.peak();
+    out->tables_resident = S->tables.size();
+    return WRS_OK;
+}
+
+extern "C" int wrs_serve_destroy(void* srv) {
+    auto* S = (Server*)srv;
+    if (!S) return WRS_EINVAL;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stop = true;
+        S->cv.notify_all();
+    }
+    if (S->worker.joinable()) S->worker.join();
+    for (auto& kv : S->tables)
+        if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+    for (auto st : S->streams) (void)hipStreamDestroy(st);
+    for (auto p : S->staging)
+        if (p) (void)hipHostFree(p);
+    delete S;
+    return WRS_OK;
+}

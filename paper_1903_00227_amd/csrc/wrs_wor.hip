@@ -1,0 +1,574 @@
+// wrs_wor.hip -- sampling without replacement by exponential clocks (Section 2.3).
+//
+// key_i = -ln(u_i) / w_i with u_i = (x0 + 1) 2^-32 from Philox counter
+// (i, stream_id, 1); the k smallest keys (ties: smaller index) are the sample.
+// Keys are generated once, in one pass over the weights:
+//   k_wor_tau     threshold tau with E[#{key <= tau}] ~ 1.02 k + 4 sqrt(k) + 64,
+//                 from a strided subsample of the weights (Newton on the
+//                 expected count sum_i 1 - exp(-w_i tau), which is concave)
+//   k_wor_filter  Philox per item; since -ln(u) >= 1 - u, an item with
+//                 1 - u > tau w cannot have key <= tau and skips the logarithm;
+//                 survivors get the exact FP64 key and are appended if <= tau.
+//                 A second, predicated pass with tau = +inf runs only if fewer
+//                 than k candidates were found.
+//   k_wor_hist / k_wor_find   radix-style select of the k-th smallest key over
+//                 the candidates: linear bins on the key, two levels of 16384
+//                 bins, until at most 8192 candidates share the target bin
+//   k_wor_gather / k_wor_final  sort that bin in LDS, take the exact k-th (key, idx)
+//   k_wor_mark    set one bit per selected item in an n-bit map
+//   k_wor_popc / k_wor_popscan / k_wor_compact   emit the set bits in index order
+#include <math.h>
+
+#include "wrs_device.h"
+
+namespace wrs {
+
+constexpr int WOR_TPB = 256;
+constexpr int WOR_IPT = 8;                       // items per thread in the filter
+constexpr int WOR_NB = 16384;                    // bins per select level
+constexpr int WOR_NLEV = 2;                      // select levels
+constexpr int WOR_SMALL = 8192;                  // final in-LDS sort capacity
+constexpr int WOR_TAU_M = 4096;                  // subsample size for tau
+constexpr int WOR_WPB = WOR_TPB * 16;            // bitmap words per compaction block
+constexpr int WOR_CAND_TPB = 256;
+
+struct WorScalars {
+    int32_t status;          // first word of the workspace, as for the build
+    uint32_t bad;
+    uint32_t count;          // candidates of the tau pass
+    uint32_t count2;         // candidates of the fallback pass
+    double tau;
+    double kkey;
+    double level_lo[WOR_NLEV];
+    double level_scale[WOR_NLEV];
+    unsigned long long maxkey_bits;
+    unsigned long long npos;
+    int64_t k;
+    int64_t rank;            // remaining 1-based rank inside the current bin
+    int32_t level_bin[WOR_NLEV];
+    int32_t nlev;            // levels used; set when resolved
+    int32_t resolved;
+    uint32_t small_count;
+    int32_t kidx;
+    uint32_t total_bits;
+};
+
+struct WorLayout {
+    size_t sc, hist, small_key, small_idx, cand_key, cand_idx, bitmap, blk, total;
+};
+
+static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static WorLayout wor_layout(int64_t n) {
+    WorLayout L;
+    size_t o = 0;
+    const int64_t nwords = cdiv(n, 32);
+    const int64_t nblk = cdiv(nwords, WOR_WPB);
+    L.sc = o;        o = a256(o + sizeof(WorScalars));
+    L.hist = o;      o = a256(o + sizeof(uint32_t) * WOR_NB * WOR_NLEV);
+    L.small_key = o; o = a256(o + sizeof(double) * WOR_SMALL);
+    L.small_idx = o; o = a256(o + sizeof(int32_t) * WOR_SMALL);
+    L.cand_key = o;  o = a256(o + sizeof(double) * n);
+    L.cand_idx = o;  o = a256(o + sizeof(int32_t) * n);
+    L.bitmap = o;    o = a256(o + sizeof(uint32_t) * nwords);
+    L.blk = o;       o = a256(o + sizeof(uint32_t) * (nblk + 1));
+    L.total = o;
+    return L;
+}
+
+size_t wor_ws_bytes(int64_t n, int64_t) { return wor_layout(n).total; }
+int wor_status_offset() { return (int)offsetof(WorScalars, status); }
+
+struct WorArgs {
+    const float* w;
+    int64_t n;
+    int64_t k;
+    uint64_t seed;
+    uint32_t sid;
+    int32_t* out;
+    WorScalars* S;
+    uint32_t* hist;
+    double* skey;
+    int32_t* sidx;
+    double* ckey;
+    int32_t* cidx;
+    uint32_t* bitmap;
+    uint32_t* blk;
+    int64_t nwords;
+};
+
+__device__ __forceinline__ uint32_t wor_x0(const WorArgs& A, int64_t i) {
+    const uint4 x = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)((uint64_t)i >> 32), A.sid, 1u),
+                                  (uint32_t)A.seed, (uint32_t)(A.seed >> 32));
+    return x.x;
+}
+
+// -ln(u) for u = (x0 + 1) 2^-32, accurate near u = 1 through log1p.
+__device__ __forceinline__ double neg_log_u(uint32_t x0) {
+    if (x0 >= 0x7FFFFFFFu) {  // u >= 1/2
+        const double d = (double)(0xFFFFFFFFu - x0) * (1.0 / 4294967296.0);  // 1 - u, exact
+        return -log1p(-d);
+    }
+    return -log(((double)x0 + 1.0) * (1.0 / 4294967296.0));
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_wor_tau(WorArgs A) {
+    __shared__ double red[32];
+    WorScalars* S = A.S;
+    // reset state (the whole select pipeline starts from here)
+    for (int i = threadIdx.x; i < WOR_NB * WOR_NLEV; i += blockDim.x) A.hist[i] = 0;
+    if (threadIdx.x == 0) {
+        S->status = WRS_OK;
+        S->bad = 0;
+        S->count = 0;
+        S->count2 = 0;
+        S->maxkey_bits = 0;
+        S->npos = 0;
+        S->k = A.k;
+        S->rank = A.k;
+        S->resolved = 0;
+        S->nlev = 0;
+        S->small_count = 0;
+        S->total_bits = 0;
+        S->kkey = 0.0;
+        S->kidx = -1;
+    }
+    const int64_t n = A.n;
+    const int m = (int)min((int64_t)WOR_TAU_M, n);
+    const double stride = (double)n / (double)m;
+    const double kt = (double)A.k * 1.02 + 4.0 * sqrt((double)A.k) + 64.0;
+    const double scale = (double)n / (double)m;
+    // local weights
+    double wl[WOR_TAU_M / 1024];
+    double wsum = 0.0;
+    for (int e = 0; e < WOR_TAU_M / 1024; ++e) {
+        const int s = threadIdx.x + e * 1024;
+        double v = 0.0;
+        if (s < m) {
+            const int64_t i = min((int64_t)((double)s * stride), n - 1);
+            const float f = A.w[i];
+            v = (f > 0.0f && !isinf(f)) ? (double)f : 0.0;
+        }
+        wl[e] = v;
+        wsum += v;
+    }
+    auto block_sum = [&](double x) -> double {
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        const int wv = threadIdx.x >> 6;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[wv] = x;
+        __syncthreads();
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+        return t;
+    };
+    const double W = block_sum(wsum) * scale;
+    double tau;
+    if (!(W > 0.0) || kt >= 0.5 * (double)n) {
+        tau = INFINITY;
+    } else {
+        tau = kt / W;  // F(tau) <= kt; Newton from below on a concave F
+        for (int it = 0; it < 40; ++it) {
+            double f = 0.0, fp = 0.0;
+            for (int e = 0; e < WOR_TAU_M / 1024; ++e) {
+                const double v = wl[e];
+                const double ex = exp(-v * tau);
+                f += -expm1(-v * tau);
+                fp += v * ex;
+            }
+            const double F = block_sum(f) * scale;
+            const double Fp = block_sum(fp) * scale;
+            if (!(Fp > 0.0)) { tau = INFINITY; break; }
+            const double step = (kt - F) / Fp;
+            tau += step;
+            if (fabs(kt - F) < 0.25 || step <= tau * 1e-12) break;
+        }
+        if (!(tau < INFINITY)) tau = INFINITY;
+    }
+    if (threadIdx.x == 0) S->tau = tau;
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WOR_TPB) void k_wor_filter(WorArgs A, int pass) {
+    __shared__ double s_max[WOR_TPB / 64];
+    __shared__ unsigned long long s_pos[WOR_TPB / 64];
+    __shared__ uint32_t s_bad[WOR_TPB / 64];
+    WorScalars* S = A.S;
+    if (pass == 2) {
+        if (S->status != WRS_OK || (int64_t)S->count >= A.k) return;
+    }
+    const double tau = (pass == 2) ? (double)INFINITY : S->tau;
+    uint32_t* counter = (pass == 2) ? &S->count2 : &S->count;
+    const int64_t n = A.n;
+    if (pass == 1) {  // clear this block's share of the bitmap
+        const int64_t per = cdiv(A.nwords, (int64_t)gridDim.x);
+        const int64_t w0 = (int64_t)blockIdx.x * per;
+        const int64_t w1 = min(A.nwords, w0 + per);
+        for (int64_t i = w0 + threadIdx.x; i < w1; i += WOR_TPB) A.bitmap[i] = 0u;
+    }
+    const int lane = threadIdx.x & 63;
+    double kmax = 0.0;
+    uint32_t bad = 0;
+    unsigned long long pos = 0;
+    const int64_t base = (int64_t)blockIdx.x * (WOR_TPB * WOR_IPT);
+#pragma unroll 2
+    for (int e = 0; e < WOR_IPT; ++e) {
+        const int64_t i = base + (int64_t)e * WOR_TPB + threadIdx.x;
+        bool cand = false;
+        double key = 0.0;
+        if (i < n) {
+            const float v = A.w[i];
+            bad |= (uint32_t)(!(v >= 0.0f) || isinf(v));
+            if (v > 0.0f && !isinf(v)) {
+                ++pos;
+                const uint32_t x0 = wor_x0(A, i);
+                const double omu = (double)(0xFFFFFFFFu - x0) * (1.0 / 4294967296.0);  // 1 - u
+                if (omu <= tau * (double)v * (1.0 + 1e-12)) {
+                    key = neg_log_u(x0) / (double)v;
+                    cand = key <= tau;
+                }
+            }
+        }
+        const unsigned long long mask = __ballot(cand);
+        if (mask) {
+            const uint32_t cnt = (uint32_t)__popcll(mask);
+            const int leader = __ffsll((long long)mask) - 1;
+            uint32_t b = 0;
+            if (lane == leader) b = atomicAdd(counter, cnt);
+            b = __shfl(b, leader, 64);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            if (cand) {
+                const uint32_t p = b + rank;
+                if ((int64_t)p < n) {
+                    A.ckey[p] = key;
+                    A.cidx[p] = (int32_t)i;
+                }
+                kmax = fmax(kmax, key);
+            }
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        kmax = fmax(kmax, __shfl_xor(kmax, off, 64));
+        bad |= __shfl_xor(bad, off, 64);
+        pos += __shfl_xor(pos, off, 64);
+    }
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_max[wv] = kmax;
+        s_bad[wv] = bad;
+        s_pos[wv] = pos;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < WOR_TPB / 64; ++k) {
+            kmax = fmax(kmax, s_max[k]);
+            bad |= s_bad[k];
+            pos += s_pos[k];
+        }
+        kmax = fmax(kmax, s_max[0]);
+        bad |= s_bad[0];
+        if (kmax > 0.0) atomicMax(&S->maxkey_bits, (unsigned long long)__double_as_longlong(kmax));
+        if (pass == 1) {
+            if (bad) atomicOr(&S->bad, 1u);
+            atomicAdd(&S->npos, (unsigned long long)(s_pos[0] + s_pos[1] + s_pos[2] + s_pos[3]));
+        }
+    }
+}
+
+// Number of candidates of the pass that holds the answer.
+__device__ __forceinline__ uint32_t wor_ncand(const WorScalars* S) {
+    return ((int64_t)S->count >= S->k) ? S->count : S->count2;
+}
+
+__device__ __forceinline__ int wor_bin(double key, double lo, double scale) {
+    const double b = floor((key - lo) * scale);
+    return (int)fmin(fmax(b, 0.0), (double)(WOR_NB - 1));
+}
+
+// Does candidate key fall into the chosen bins of levels [0, upto)?
+__device__ __forceinline__ bool wor_in_set(const WorScalars* S, double key, int upto) {
+    for (int l = 0; l < upto; ++l)
+        if (wor_bin(key, S->level_lo[l], S->level_scale[l]) != S->level_bin[l]) return false;
+    return true;
+}
+
+__global__ __launch_bounds__(WOR_CAND_TPB) void k_wor_hist(WorArgs A, int level) {
+    __shared__ uint32_t h[WOR_NB];
+    WorScalars* S = A.S;
+    if (S->status != WRS_OK || S->resolved || S->bad) return;
+    const uint32_t nc = wor_ncand(S);
+    if ((int64_t)nc < A.k) return;
+    double lo, scale;
+    if (level == 0) {
+        const double mx = __longlong_as_double((long long)S->maxkey_bits);
+        lo = 0.0;
+        scale = (mx > 0.0) ? (double)WOR_NB / (mx * (1.0 + 1e-9)) : 1.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            S->level_lo[0] = lo;
+            S->level_scale[0] = scale;
+        }
+    } else {
+        lo = S->level_lo[level];
+        scale = S->level_scale[level];
+    }
+    for (int i = threadIdx.x; i < WOR_NB; i += WOR_CAND_TPB) h[i] = 0;
+    __syncthreads();
+    for (int64_t c = (int64_t)blockIdx.x * WOR_CAND_TPB + threadIdx.x; c < nc; c += (int64_t)gridDim.x * WOR_CAND_TPB) {
+        const double key = A.ckey[c];
+        if (level == 0 || wor_in_set(S, key, level)) atomicAdd(&h[wor_bin(key, lo, scale)], 1u);
+    }
+    __syncthreads();
+    uint32_t* g = A.hist + (size_t)level * WOR_NB;
+    for (int i = threadIdx.x; i < WOR_NB; i += WOR_CAND_TPB)
+        if (h[i]) atomicAdd(&g[i], h[i]);
+}
+
+__global__ __launch_bounds__(1024) void k_wor_find(WorArgs A, int level) {
+    __shared__ uint32_t part[1024];
+    WorScalars* S = A.S;
+    if (threadIdx.x == 0) {
+        // domain checks once every candidate pass is complete
+        if (S->status == WRS_OK && S->bad) S->status = WRS_EDOMAIN;
+        if (S->status == WRS_OK && (int64_t)wor_ncand(S) < A.k) S->status = WRS_EDOMAIN;
+    }
+    __syncthreads();
+    if (S->status != WRS_OK || S->resolved) return;
+    const uint32_t* g = A.hist + (size_t)level * WOR_NB;
+    constexpr int PER = WOR_NB / 1024;
+    uint32_t local = 0;
+    for (int e = 0; e < PER; ++e) local += g[threadIdx.x * PER + e];
+    part[threadIdx.x] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t rank = S->rank;
+        int64_t cum = 0;
+        int t = 0;
+        while (t < 1023 && cum + part[t] < rank) cum += part[t++];
+        int b = t * PER;
+        while (b < (t + 1) * PER - 1 && cum + g[b] < rank) cum += g[b++];
+        const uint32_t cnt = g[b];
+        S->rank = rank - cum;
+        S->level_bin[level] = b;
+        if (cnt <= (uint32_t)WOR_SMALL) {
+            S->resolved = 1;
+            S->nlev = level + 1;
+            S->small_count = 0;
+        } else if (level + 1 < WOR_NLEV) {
+            const double lo = S->level_lo[level], sc = S->level_scale[level];
+            S->level_lo[level + 1] = lo + (double)b / sc;
+            S->level_scale[level + 1] = sc * (double)WOR_NB;
+        } else {
+            S->status = WRS_EDEVICE;  // more than WOR_SMALL keys tie at the boundary
+        }
+    }
+}
+
+__global__ __launch_bounds__(WOR_CAND_TPB) void k_wor_gather(WorArgs A) {
+    WorScalars* S = A.S;
+    if (S->status != WRS_OK || !S->resolved) return;
+    const uint32_t nc = wor_ncand(S);
+    const int nlev = S->nlev;
+    for (int64_t c = (int64_t)blockIdx.x * WOR_CAND_TPB + threadIdx.x; c < nc; c += (int64_t)gridDim.x * WOR_CAND_TPB) {
+        const double key = A.ckey[c];
+        if (wor_in_set(S, key, nlev)) {
+            const uint32_t p = atomicAdd(&S->small_count, 1u);
+            if (p < (uint32_t)WOR_SMALL) {
+                A.skey[p] = key;
+                A.sidx[p] = A.cidx[c];
+            }
+        }
+    }
+}
+
+// Bitonic sort of the bin in LDS by (key, idx); the rank-th element is the
+// last one selected.
+__global__ __launch_bounds__(1024) void k_wor_final(WorArgs A) {
+    __shared__ double sk[WOR_SMALL];
+    __shared__ int32_t si[WOR_SMALL];
+    WorScalars* S = A.S;
+    if (S->status != WRS_OK || !S->resolved) return;
+    const int m = (int)min(S->small_count, (uint32_t)WOR_SMALL);
+    int P = 1;
+    while (P < m) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        if (i < m) {
+            sk[i] = A.skey[i];
+            si[i] = A.sidx[i];
+        } else {
+            sk[i] = INFINITY;
+            si[i] = 0x7fffffff;
+        }
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const bool gt = sk[i] > sk[j] || (sk[i] == sk[j] && si[i] > si[j]);
+                    if (gt == up) {
+                        const double tk = sk[i];
+                        sk[i] = sk[j];
+                        sk[j] = tk;
+                        const int32_t ti = si[i];
+                        si[i] = si[j];
+                        si[j] = ti;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        const int64_t r = S->rank;  // 1-based
+        if (r < 1 || r > m) {
+            S->status = WRS_EDEVICE;
+        } else {
+            S->kkey = sk[r - 1];
+            S->kidx = si[r - 1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(WOR_CAND_TPB) void k_wor_mark(WorArgs A) {
+    WorScalars* S = A.S;
+    if (S->status != WRS_OK) return;
+    const uint32_t nc = wor_ncand(S);
+    const double kk = S->kkey;
+    const int32_t ki = S->kidx;
+    for (int64_t c = (int64_t)blockIdx.x * WOR_CAND_TPB + threadIdx.x; c < nc; c += (int64_t)gridDim.x * WOR_CAND_TPB) {
+        const double key = A.ckey[c];
+        const int32_t idx = A.cidx[c];
+        if (key < kk || (key == kk && idx <= ki)) atomicOr(&A.bitmap[idx >> 5], 1u << (idx & 31));
+    }
+}
+
+__global__ __launch_bounds__(WOR_TPB) void k_wor_popc(WorArgs A) {
+    __shared__ uint32_t s[WOR_TPB / 64];
+    if (A.S->status != WRS_OK) return;
+    const int64_t w0 = (int64_t)blockIdx.x * WOR_WPB;
+    uint32_t c = 0;
+    for (int e = 0; e < WOR_WPB / WOR_TPB; ++e) {
+        const int64_t i = w0 + (int64_t)e * WOR_TPB + threadIdx.x;
+        if (i < A.nwords) c += __popc(A.bitmap[i]);
+    }
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) A.blk[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+__global__ __launch_bounds__(1024) void k_wor_popscan(WorArgs A, int nblk) {
+    __shared__ uint32_t s[1024];
+    WorScalars* S = A.S;
+    if (S->status != WRS_OK) return;
+    // exclusive scan of nblk block totals, sequential per thread chunk
+    const int per = (nblk + 1023) / 1024;
+    uint32_t loc = 0;
+    for (int e = 0; e < per; ++e) {
+        const int i = threadIdx.x * per + e;
+        if (i < nblk) loc += A.blk[i];
+    }
+    s[threadIdx.x] = loc;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t v = (threadIdx.x >= (unsigned)d) ? s[threadIdx.x - d] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = s[threadIdx.x] - loc;
+    for (int e = 0; e < per; ++e) {
+        const int i = threadIdx.x * per + e;
+        if (i < nblk) {
+            const uint32_t v = A.blk[i];
+            A.blk[i] = run;
+            run += v;
+        }
+    }
+    if (threadIdx.x == 1023) {
+        S->total_bits = s[1023];
+        if ((int64_t)s[1023] != A.k) S->status = WRS_EDEVICE;
+    }
+}
+
+__global__ __launch_bounds__(WOR_TPB) void k_wor_compact(WorArgs A) {
+    __shared__ uint32_t s[WOR_TPB / 64];
+    if (A.S->status != WRS_OK) return;
+    constexpr int PER = WOR_WPB / WOR_TPB;  // consecutive words per thread
+    const int64_t w0 = (int64_t)blockIdx.x * WOR_WPB + (int64_t)threadIdx.x * PER;
+    uint32_t words[PER];
+    uint32_t c = 0;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int64_t i = w0 + e;
+        words[e] = (i < A.nwords) ? A.bitmap[i] : 0u;
+        c += __popc(words[e]);
+    }
+    // block exclusive scan of c
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t incl = c;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) s[wv] = incl;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int k = 0; k < wv; ++k) pre += s[k];
+    uint32_t p = A.blk[blockIdx.x] + pre + incl - c;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        uint32_t wd = words[e];
+        while (wd) {
+            const int b = __ffs(wd) - 1;
+            wd &= wd - 1;
+            A.out[p++] = (int32_t)((w0 + e) * 32 + b);
+        }
+    }
+}
+
+int launch_wor(const float* w, int64_t n, int64_t k, uint64_t seed, uint32_t sid, int32_t* out, void* ws,
+               hipStream_t st) {
+    const WorLayout L = wor_layout(n);
+    char* b = (char*)ws;
+    WorArgs A;
+    A.w = w;
+    A.n = n;
+    A.k = k;
+    A.seed = seed;
+    A.sid = sid;
+    A.out = out;
+    A.S = (WorScalars*)(b + L.sc);
+    A.hist = (uint32_t*)(b + L.hist);
+    A.skey = (double*)(b + L.small_key);
+    A.sidx = (int32_t*)(b + L.small_idx);
+    A.ckey = (double*)(b + L.cand_key);
+    A.cidx = (int32_t*)(b + L.cand_idx);
+    A.bitmap = (uint32_t*)(b + L.bitmap);
+    A.blk = (uint32_t*)(b + L.blk);
+    A.nwords = cdiv(n, 32);
+    const int64_t fblocks = cdiv(n, (int64_t)WOR_TPB * WOR_IPT);
+    const int nblk = (int)cdiv(A.nwords, WOR_WPB);
+    // candidate kernels: enough blocks to fill the chip, few enough for cheap atomics
+    const int cblocks = 512;
+    hipLaunchKernelGGL(k_wor_tau, dim3(1), dim3(1024), 0, st, A);
+    hipLaunchKernelGGL(k_wor_filter, dim3((unsigned)fblocks), dim3(WOR_TPB), 0, st, A, 1);
+    hipLaunchKernelGGL(k_wor_filter, dim3((unsigned)fblocks), dim3(WOR_TPB), 0, st, A, 2);
+    for (int l = 0; l < WOR_NLEV; ++l) {
+        hipLaunchKernelGGL(k_wor_hist, dim3(cblocks), dim3(WOR_CAND_TPB), 0, st, A, l);
+        hipLaunchKernelGGL(k_wor_find, dim3(1), dim3(1024), 0, st, A, l);
+    }
+    hipLaunchKernelGGL(k_wor_gather, dim3(cblocks), dim3(WOR_CAND_TPB), 0, st, A);
+    hipLaunchKernelGGL(k_wor_final, dim3(1), dim3(1024), 0, st, A);
+    hipLaunchKernelGGL(k_wor_mark, dim3(cblocks), dim3(WOR_CAND_TPB), 0, st, A);
+    hipLaunchKernelGGL(k_wor_popc, dim3(nblk), dim3(WOR_TPB), 0, st, A);
+    hipLaunchKernelGGL(k_wor_popscan, dim3(1), dim3(1024), 0, st, A, nblk);
+    hipLaunchKernelGGL(k_wor_compact, dim3(nblk), dim3(WOR_TPB), 0, st, A);
+    return hipGetLastError() == hipSuccess ? WRS_OK : WRS_EDEVICE;
+}
+
+}  // namespace wrs
