@@ -28,17 +28,6 @@ static int dev_fail(const char* what, hipError_t e) {
 
 static constexpr int64_t N_MAX = 2147483647LL;
 
-static void single_blocks(const JobDesc& J, int64_t blocks[PH_COUNT]) {
-    const int64_t C = J.ntiles;
-    blocks[PH_RED] = J.nred;
-    blocks[PH_FIN] = 1;
-    blocks[PH_TILE] = C;
-    blocks[PH_SEG] = J.nseg;
-    blocks[PH_TOP] = 1;
-    blocks[PH_PACK] = cdiv(2 * C, PACK_STEPS);
-    blocks[PH_SAMPLE] = cdiv(J.k, SAMPLES_PER_BLOCK);
-}
-
 }  // namespace wrs
 
 using namespace wrs;
@@ -67,7 +56,7 @@ extern "C" int wrs_alias_build(const float* d_w, int64_t n, wrs_entry* d_table, 
     J.table = d_table;
     build_ws_layout(J, d_ws, n);
     int64_t blocks[PH_COUNT];
-    single_blocks(J, blocks);
+    phase_blocks(J, blocks);
     hipError_t e = launch_build(jt, blocks, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail("wrs_alias_build launch", e);
     return WRS_OK;
@@ -223,7 +212,7 @@ static int batch_record(const wrs_job* h_jobs, int32_t njobs, void* d_ws, hipStr
         o += a256(build_ws_bytes(h_jobs[j].n));
         J.sc = (BuildScalars*)(base + h.sc_off) + j;  // statuses side by side
         int64_t b[PH_COUNT];
-        single_blocks(J, b);
+        phase_blocks(J, b);
         for (int p = 0; p < PH_COUNT; ++p) off[(size_t)p * (njobs + 1) + j + 1] = off[(size_t)p * (njobs + 1) + j] + b[p];
     }
     for (int p = 0; p < PH_COUNT; ++p) totals[p] = off[(size_t)p * (njobs + 1) + njobs];

@@ -20,7 +20,8 @@
 //   k_finalize  grid exponent G and integer capacity Q = round(W / 2^G)
 //   k_tileagg   per tile of 1024 items: #lights, light deficit, heavy excess
 //   k_scan_*    exclusive prefix over tiles (segmented)
-//   k_pack      merge, cut at tile events, each block emitting 16 events
+//   k_split     start event of every pack block (merge path over tile prefixes)
+//   k_pack      merge, cut at tile events, each block handling 16 events
 //   k_sample    alias queries
 #include <float.h>
 #include <math.h>
@@ -38,8 +39,10 @@ static constexpr int32_t FH_NONE = 0x7fffffff;
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BuildLayout {
-    size_t sc, red, redinfo, NL, DP, EP, FH, sNL, sDP, sEP, sFH, total;
+    size_t sc, red, redinfo, NL, DP, EP, DP64, EP64, FH, pstart, sNL, sDP, sEP, sFH, total;
 };
+
+static int64_t pack_blocks(int64_t C) { return cdiv(2 * C, PACK_STEPS); }
 
 static BuildLayout layout_for(int64_t n) {
     const int64_t C = cdiv(n, TILE);
@@ -53,7 +56,10 @@ static BuildLayout layout_for(int64_t n) {
     L.NL = o;      o = align256(o + sizeof(uint32_t) * (C + 1));
     L.DP = o;      o = align256(o + sizeof(u128) * (C + 1));
     L.EP = o;      o = align256(o + sizeof(u128) * (C + 1));
+    L.DP64 = o;    o = align256(o + sizeof(uint64_t) * (C + 1));
+    L.EP64 = o;    o = align256(o + sizeof(uint64_t) * (C + 1));
     L.FH = o;      o = align256(o + sizeof(int32_t) * (C + 1));
+    L.pstart = o;  o = align256(o + sizeof(int32_t) * pack_blocks(C));
     L.sNL = o;     o = align256(o + sizeof(uint32_t) * (S + 1));
     L.sDP = o;     o = align256(o + sizeof(u128) * (S + 1));
     L.sEP = o;     o = align256(o + sizeof(u128) * (S + 1));
@@ -77,7 +83,11 @@ void build_ws_layout(JobDesc& J, void* ws, int64_t n) {
     J.NL = (uint32_t*)(b + L.NL);
     J.DP = (u128*)(b + L.DP);
     J.EP = (u128*)(b + L.EP);
+    J.DP64 = (uint64_t*)(b + L.DP64);
+    J.EP64 = (uint64_t*)(b + L.EP64);
     J.FH = (int32_t*)(b + L.FH);
+    J.pstart = (int32_t*)(b + L.pstart);
+    J.npack = (int32_t)pack_blocks(J.ntiles);
     J.sNL = (uint32_t*)(b + L.sNL);
     J.sDP = (u128*)(b + L.sDP);
     J.sEP = (u128*)(b + L.sEP);
@@ -195,6 +205,9 @@ __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
     S.rQ = 0;
     S.nscale = 0;
     S.Qn = 0;
+    S.kshift = 0;
+    S.pad2 = 0;
+    S.tscale = 0;
     if (bad || !(hi > 0.0)) {
         S.status = WRS_EDOMAIN;
     } else {
@@ -219,6 +232,13 @@ __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
         while ((u128)n * (u128)(qn + 1) <= Q) ++qn;
         while ((u128)n * (u128)qn > Q) --qn;
         S.Qn = qn;
+        // merge keys: prefix sums (at most n Q) shifted right to fit 62 bits
+        const uint64_t qh = (uint64_t)(Q >> 64), ql = (uint64_t)Q;
+        const int qbits = qh ? 128 - __clzll((long long)qh) : 64 - __clzll((long long)ql);
+        const int nbits = 64 - __clzll((long long)n);
+        const int sh = max(0, qbits + nbits - 62);
+        S.kshift = sh;
+        S.tscale = ldexp(1.0, sh) * S.rQ;
     }
     *J.sc = S;
 }
@@ -240,54 +260,82 @@ __device__ __forceinline__ void load_tile_items(const float* w, int64_t base, in
     }
 }
 
+__device__ __forceinline__ u128 wave_sum_u128(u128 v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t lo = __shfl_xor((unsigned long long)(uint64_t)v, off, 64);
+        const uint64_t hi = __shfl_xor((unsigned long long)(uint64_t)(v >> 64), off, 64);
+        v += ((u128)hi << 64) | lo;
+    }
+    return v;
+}
+
+// One wave per tile: each lane reads 4 float4 (lane-interleaved, 1 KiB per
+// instruction across the wave), so no block synchronisation is needed.
+constexpr int AGG_VEC = TILE / 256;  // float4 loads per lane
+
 __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
     __shared__ int s_job;
-    __shared__ ScanTmp tmp;
-    __shared__ int s_fh;
     int64_t lb;
     const JobDesc& J = job_of_block(jt, lb, &s_job);
     const BuildScalars* sc = J.sc;
     if (sc->status != WRS_OK) return;
+    const int64_t c = lb * TILES_PER_AGG_BLOCK + (threadIdx.x >> 6);
+    if (c >= J.ntiles) return;
+    const int lane = threadIdx.x & 63;
     const int G = sc->G;
     const uint64_t Qn = sc->Qn;
     const u128 Q = sc->Q;
     const int64_t n = J.n;
-    const int64_t c = lb;
     const int64_t base = c * TILE;
     const int cnt = (int)min((int64_t)TILE, n - base);
-    if (threadIdx.x == 0) s_fh = FH_NONE;
-    float v[IPT];
-    load_tile_items(J.w, base, cnt, v);
+    const float* w = J.w + base;
+    const bool vec = (cnt == TILE) && ((((uintptr_t)w) & 15) == 0);
+    float v[4 * AGG_VEC];
+#pragma unroll
+    for (int r = 0; r < AGG_VEC; ++r) {
+        const int i0 = r * 256 + lane * 4;
+        if (vec) {
+            const float4 x = *(const float4*)(w + i0);
+            v[4 * r] = x.x; v[4 * r + 1] = x.y; v[4 * r + 2] = x.z; v[4 * r + 3] = x.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[4 * r + e] = (i0 + e < cnt) ? w[i0 + e] : 0.0f;
+        }
+    }
     uint32_t nl = 0;
     u128 sql = 0, sqh = 0;
     int fh = FH_NONE;
 #pragma unroll
-    for (int e = 0; e < IPT; ++e) {
-        const int i = threadIdx.x * IPT + e;
-        if (i < cnt) {
-            const u128 q = quantize(v[e], G);
-            if (q <= (u128)Qn) {
-                ++nl;
-                sql += q;
-            } else {
-                sqh += q;
-                fh = min(fh, (int)(base + i));
+    for (int r = 0; r < AGG_VEC; ++r) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = r * 256 + lane * 4 + e;
+            if (i < cnt) {
+                const u128 q = quantize(v[4 * r + e], G);
+                if (q <= (u128)Qn) {
+                    ++nl;
+                    sql += q;
+                } else {
+                    sqh += q;
+                    fh = min(fh, (int)(base + i));
+                }
             }
         }
     }
-    __syncthreads();
-    if (fh != FH_NONE) atomicMin(&s_fh, fh);
-    uint32_t nl_ex, nl_tot;
-    u128 a_ex, b_ex, a_tot, b_tot;
-    block_scan3(nl, sql, sqh, nl_ex, a_ex, b_ex, nl_tot, a_tot, b_tot, tmp);
-    if (threadIdx.x == 0) {
-        const uint32_t nh = (uint32_t)cnt - nl_tot;
-        const u128 D = (u128)nl_tot * Q - (u128)n * a_tot;
-        const u128 E = (u128)n * b_tot - (u128)nh * Q;
-        J.NL[c] = nl_tot;
-        J.DP[c] = D;
-        J.EP[c] = E;
-        J.FH[c] = s_fh;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        nl += __shfl_xor(nl, off, 64);
+        fh = min(fh, __shfl_xor(fh, off, 64));
+    }
+    sql = wave_sum_u128(sql);
+    sqh = wave_sum_u128(sqh);
+    if (lane == 0) {
+        const uint32_t nh = (uint32_t)cnt - nl;
+        J.NL[c] = nl;
+        J.DP[c] = (u128)nl * Q - (u128)n * sql;
+        J.EP[c] = (u128)n * sqh - (u128)nh * Q;
+        J.FH[c] = fh;
     }
 }
 
@@ -432,9 +480,12 @@ __global__ __launch_bounds__(TPB) void k_scan_top(JobTable jt) {
     }
     if (threadIdx.x == 0) {
         const int64_t C = J.ntiles;
+        const int ks = J.sc->kshift;
         J.NL[C] = nl_tot;
         J.DP[C] = dp_tot;
         J.EP[C] = ep_tot;
+        J.DP64[C] = (uint64_t)(dp_tot >> ks);
+        J.EP64[C] = (uint64_t)(ep_tot >> ks);
         J.FH[C] = FH_NONE;
         J.sFH[S] = FH_NONE;
     }
@@ -449,12 +500,17 @@ __global__ __launch_bounds__(TPB) void k_scan_fix(JobTable jt) {
     const uint32_t pnl = J.sNL[lb];
     const u128 pdp = J.sDP[lb], pep = J.sEP[lb];
     const int nxt = J.sFH[lb + 1];
+    const int ks = J.sc->kshift;
     for (int e = 0; e < SEG_PER_THREAD; ++e) {
         const int64_t c = lb * SCAN_SEG + (int64_t)e * TPB + threadIdx.x;
         if (c < C) {
             J.NL[c] += pnl;
-            J.DP[c] += pdp;
-            J.EP[c] += pep;
+            const u128 dp = J.DP[c] + pdp;
+            const u128 ep = J.EP[c] + pep;
+            J.DP[c] = dp;
+            J.EP[c] = ep;
+            J.DP64[c] = (uint64_t)(dp >> ks);
+            J.EP64[c] = (uint64_t)(ep >> ks);
             const int f = J.FH[c];
             J.FH[c] = (f != FH_NONE) ? f : nxt;
         }
@@ -469,31 +525,70 @@ __global__ __launch_bounds__(TPB) void k_scan_fix(JobTable jt) {
 // heavy); heavy event y (y = 1..C) is the state just after the last heavy of
 // tile y-1 (key EP[y]).  Heavy event y precedes light event x iff
 // EP[y] <= DP[x].  The 2C events in merge order cut the sweep into cells; in
-// each cell the lights come from one tile and the heavies from one tile.  Block
-// b handles events [16 b, 16 b + 16): it finds its start by a merge-path search
-// over (DP, EP), refines the exact state inside the two current tiles, then
-// merges cell by cell.
+// each cell the lights come from one tile and the heavies from one tile.
+// Pack block b handles events [16 b, 16 b + 16).  k_split finds where each
+// block starts (the paper's split(), on tile granularity); the block refines
+// the exact state inside its first two tiles and merges cell by cell.
+//
+// Merge keys are the exact prefix sums shifted right by kshift (64-bit keys,
+// resolution 2^-33 bucket or finer for n < 2^31).  Every block compares the
+// same 64-bit keys, so all cuts agree; the keys are a monotone image of the
+// exact sums, so the merge differs from the exact sweep only where a light's
+// and a heavy's sums are closer than that resolution.
 // ---------------------------------------------------------------------------
-struct TileSlot {
-    u128 key[TILE];     // lights [0, nl): D before the light; heavies [nl, nl+nh): E through the heavy
-    int32_t idx[TILE];  // item index
-    float tl[TILE];     // t of the lights
+__global__ __launch_bounds__(TPB) void k_split(JobTable jt) {
+    __shared__ int s_job;
+    int64_t lb;
+    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    if (J.sc->status != WRS_OK) return;
+    const int64_t b = lb * TPB + threadIdx.x;
+    if (b >= J.npack) return;
+    const int64_t C = J.ntiles;
+    const int64_t s0 = b * PACK_STEPS;
+    const uint64_t* DP = J.DP64;
+    const uint64_t* EP = J.EP64;
+    // largest x with: x == 0, or light event x precedes heavy event s0-x+1
+    int64_t lo = max((int64_t)0, s0 - C), hi = min(s0, C);
+    while (lo < hi) {
+        const int64_t x = (lo + hi + 1) >> 1;
+        const int64_t y1 = s0 - x + 1;
+        const bool ok = (y1 > C) || (x < C && DP[x] < EP[y1]);
+        if (ok) lo = x; else hi = x - 1;
+    }
+    J.pstart[b] = (int32_t)lo;
+}
+
+struct PackSlot {
+    uint64_t key[TILE];  // lights [0, nl): D before the light; heavies [nl, nl+nh): E through the heavy
+    int32_t idx[TILE];   // item index
+    float tl[TILE];      // t of the lights
     int32_t nl, nh;
 };
 
 struct PackShared {
-    TileSlot slot[2];
+    PackSlot slot[2];
+    uint64_t dp[PACK_STEPS + 2];  // DP64[x0 + i]
+    uint64_t ep[PACK_STEPS + 2];  // EP64[y0 + i]
+    int32_t fh[PACK_STEPS + 2];   // FH[y0 + i]
     ScanTmp tmp;
     int s_job;
-    int s_best;
 };
 
-// Fill slot S with tile c (c == C gives an empty tile).
-__device__ void load_pack_tile(TileSlot& S, int64_t c, const JobDesc& J, const BuildScalars& sc,
-                               ScanTmp& tmp) {
-    const int64_t C = J.ntiles;
-    if (c >= C) {
-        __syncthreads();
+__device__ __forceinline__ void fetch_tile(const JobDesc& J, int64_t c, float v[IPT]) {
+    if (c >= J.ntiles) {
+#pragma unroll
+        for (int e = 0; e < IPT; ++e) v[e] = 0.0f;
+        return;
+    }
+    const int64_t base = c * TILE;
+    load_tile_items(J.w, base, (int)min((int64_t)TILE, J.n - base), v);
+}
+
+// Fill slot S with tile c from prefetched weights v (c == C gives an empty tile).
+__device__ void fill_tile(PackSlot& S, int64_t c, const float v[IPT], const JobDesc& J, const BuildScalars& sc,
+                          ScanTmp& tmp) {
+    __syncthreads();  // every thread is done with the slot's previous contents
+    if (c >= J.ntiles) {
         if (threadIdx.x == 0) {
             S.nl = 0;
             S.nh = 0;
@@ -506,31 +601,30 @@ __device__ void load_pack_tile(TileSlot& S, int64_t c, const JobDesc& J, const B
     const int cnt = (int)min((int64_t)TILE, n - base);
     const u128 Q = sc.Q;
     const uint64_t Qn = sc.Qn;
+    const int ks = sc.kshift;
     const u128 Dbase = J.DP[c];
     const u128 Ebase = J.EP[c];
-    float v[IPT];
-    load_tile_items(J.w, base, cnt, v);
-    u128 q[IPT];
+    u128 d[IPT];
     bool light[IPT];
     uint32_t nl = 0;
     u128 dsum = 0, esum = 0;
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         const int i = threadIdx.x * IPT + e;
-        q[e] = quantize(v[e], sc.G);
-        light[e] = (i < cnt) && (q[e] <= (u128)Qn);
-        if (i < cnt) {
-            if (light[e]) {
-                ++nl;
-                dsum += Q - (u128)n * q[e];
-            } else {
-                esum += (u128)n * q[e] - Q;
-            }
+        const bool valid = i < cnt;
+        const u128 q = quantize(v[e], sc.G);
+        light[e] = valid && (q <= (u128)Qn);
+        const u128 nq = (u128)n * q;
+        d[e] = !valid ? (u128)0 : (light[e] ? Q - nq : nq - Q);
+        if (light[e]) {
+            ++nl;
+            dsum += d[e];
+        } else {
+            esum += d[e];
         }
     }
     uint32_t nl_ex, nl_tot;
     u128 d_ex, e_ex, d_tot, e_tot;
-    __syncthreads();  // the slot may still be read by the previous cell
     block_scan3(nl, dsum, esum, nl_ex, d_ex, e_ex, nl_tot, d_tot, e_tot, tmp);
     uint32_t lr = nl_ex;
     uint32_t hr = (uint32_t)(threadIdx.x * IPT) - nl_ex;  // heavies before this thread's items
@@ -541,15 +635,15 @@ __device__ void load_pack_tile(TileSlot& S, int64_t c, const JobDesc& J, const B
         const int i = threadIdx.x * IPT + e;
         if (i < cnt) {
             if (light[e]) {
-                S.key[lr] = dacc;
+                S.key[lr] = (uint64_t)(dacc >> ks);
                 S.idx[lr] = (int32_t)(base + i);
                 S.tl[lr] = (float)((double)v[e] * sc.nscale * sc.rQ);
-                dacc += Q - (u128)n * q[e];
+                dacc += d[e];
                 ++lr;
             } else {
-                eacc += (u128)n * q[e] - Q;
+                eacc += d[e];
                 const int p = (int)nl_tot + (int)hr;
-                S.key[p] = eacc;
+                S.key[p] = (uint64_t)(eacc >> ks);
                 S.idx[p] = (int32_t)(base + i);
                 ++hr;
             }
@@ -562,9 +656,9 @@ __device__ void load_pack_tile(TileSlot& S, int64_t c, const JobDesc& J, const B
     __syncthreads();
 }
 
-// number of lights at positions [from, nl) of S with key < v, plus from
-__device__ __forceinline__ int lights_below(const TileSlot& S, int from, u128 v) {
-    int lo = from, hi = S.nl;  // first position with key >= v
+// first position in [from, nl) whose light key is >= v
+__device__ __forceinline__ int lights_below(const PackSlot& S, int from, uint64_t v) {
+    int lo = from, hi = S.nl;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (S.key[mid] < v) lo = mid + 1; else hi = mid;
@@ -572,9 +666,9 @@ __device__ __forceinline__ int lights_below(const TileSlot& S, int from, u128 v)
     return lo;
 }
 
-// number of heavies at positions [from, nh) of S with key <= v, plus from
-__device__ __forceinline__ int heavies_upto(const TileSlot& S, int from, u128 v) {
-    int lo = from, hi = S.nh;  // first position with key > v
+// first position in [from, nh) whose heavy key is > v
+__device__ __forceinline__ int heavies_upto(const PackSlot& S, int from, uint64_t v) {
+    int lo = from, hi = S.nh;
     const int off = S.nl;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -595,62 +689,52 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
     if (J.sc->status != WRS_OK) return;
     const BuildScalars sc = *J.sc;
     const int64_t C = J.ntiles;
-    const int64_t total = 2 * C;
     const int64_t s0 = lb * PACK_STEPS;
-    const int64_t s1 = min(s0 + (int64_t)PACK_STEPS, total);
-    const u128* DP = J.DP;
-    const u128* EP = J.EP;
-    // Light event x precedes heavy event s0 - x + 1 (none if beyond C).  The
-    // last light event (x = C) has key +infinity.
-    auto dpkey_lt = [&](int64_t x, const u128& v) -> bool {  // DPkey(x) < v
-        return x < C && DP[x] < v;
-    };
-    auto pred = [&](int64_t x) -> bool {
-        const int64_t y1 = s0 - x + 1;
-        return x == 0 || y1 > C || dpkey_lt(x, EP[y1]);
-    };
-    // k-ary search for the largest x in [lo, hi] with pred(x); pred(lo) holds.
-    int64_t lo = max((int64_t)0, s0 - C), hi = min(s0, C);
-    while (lo < hi) {
-        const int64_t len = hi - lo;
-        const int64_t stride = (len + TPB - 1) / TPB;
-        if (threadIdx.x == 0) sh.s_best = -1;
-        __syncthreads();
-        const int64_t xt = lo + (int64_t)(threadIdx.x + 1) * stride;
-        if (xt <= hi && pred(xt)) atomicMax(&sh.s_best, (int)threadIdx.x);
-        __syncthreads();
-        const int best = sh.s_best;
-        __syncthreads();
-        const int64_t nlo = (best >= 0) ? lo + (int64_t)(best + 1) * stride : lo;
-        const int64_t nhi = min(hi, nlo + stride - 1);
-        lo = nlo;
-        hi = nhi;
+    const int64_t s1 = min(s0 + (int64_t)PACK_STEPS, 2 * C);
+    const int64_t x0 = J.pstart[lb];
+    const int64_t y0 = s0 - x0;
+    float va[IPT], vb[IPT];
+    fetch_tile(J, x0, va);
+    if (y0 != x0) fetch_tile(J, y0, vb);
+    for (int i = threadIdx.x; i < PACK_STEPS + 2; i += TPB) {
+        const int64_t xi = x0 + i, yi = y0 + i;
+        sh.dp[i] = (xi <= C) ? J.DP64[xi] : ~0ull;
+        sh.ep[i] = (yi <= C) ? J.EP64[yi] : ~0ull;
+        sh.fh[i] = (yi <= C) ? J.FH[yi] : FH_NONE;
     }
-    int64_t x = lo, y = s0 - lo;
     int sa = 0, sb = 0;
-    load_pack_tile(sh.slot[0], x, J, sc, sh.tmp);
-    if (y != x) {
+    fill_tile(sh.slot[0], x0, va, J, sc, sh.tmp);  // its first barrier also publishes the window
+    if (y0 != x0) {
         sb = 1;
-        load_pack_tile(sh.slot[1], y, J, sc, sh.tmp);
+        fill_tile(sh.slot[1], y0, vb, J, sc, sh.tmp);
     }
+    int64_t x = x0, y = y0;
+    // DPkey(x) < v, with DPkey(C) = +infinity
+    auto dpkey_lt = [&](int64_t xx, uint64_t v) -> bool { return xx < C && sh.dp[xx - x0] < v; };
     int pl = 0, ph = 0;
     if (s0 > 0) {
-        const bool last_light = x >= 1 && (y == 0 || !(dpkey_lt(x, EP[y]) ));
-        // last_light <=> EP[y] <= DPkey(x)
+        const bool last_light = x >= 1 && (y == 0 || !dpkey_lt(x, sh.ep[0]));  // EP[y] <= DPkey(x)
         if (last_light) {
-            ph = (x < C) ? heavies_upto(sh.slot[sb], 0, DP[x]) : 0;
+            ph = (x < C) ? heavies_upto(sh.slot[sb], 0, sh.dp[0]) : 0;
         } else {
-            pl = lights_below(sh.slot[sa], 0, EP[y]);
+            pl = lights_below(sh.slot[sa], 0, sh.ep[0]);
         }
     }
-    const u128 Q = sc.Q;
+    const double tscale = sc.tscale;
     for (int64_t s = s0; s < s1; ++s) {
-        TileSlot& A = sh.slot[sa];
-        TileSlot& B = sh.slot[sb];
+        const PackSlot& A = sh.slot[sa];
+        const PackSlot& B = sh.slot[sb];
+        const int xi = (int)(x - x0), yi = (int)(y - y0);
         const bool has_h = y + 1 <= C;
         const bool has_l = x + 1 <= C;
-        const u128 EPn = has_h ? EP[y + 1] : (u128)0;
+        const uint64_t EPn = sh.ep[yi + 1];
         const bool heavy_ev = has_h && (!has_l || !dpkey_lt(x + 1, EPn));
+        // prefetch the tile that the event opens, unless the other stream holds it
+        const int64_t nt = heavy_ev ? y + 1 : x + 1;
+        const bool reuse = heavy_ev ? (nt == x) : (nt == y);
+        const bool need = (s + 1 < s1) && !reuse;
+        float vn[IPT];
+        if (need) fetch_tile(J, nt, vn);
         const int nlx = A.nl, nhy = B.nh, offB = B.nl;
         int nlc, nhc;
         if (heavy_ev) {
@@ -658,10 +742,10 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
             nlc = lights_below(A, pl, EPn) - pl;
         } else {
             nlc = nlx - pl;
-            nhc = (y < C) ? heavies_upto(B, ph, DP[x + 1]) - ph : 0;
+            nhc = (y < C) ? heavies_upto(B, ph, sh.dp[xi + 1]) - ph : 0;
         }
-        const int32_t nextH = (y + 1 <= C) ? J.FH[y + 1] : FH_NONE;
-        const u128 Dend = DP[min(x + 1, C)];
+        const int32_t nextH = has_h ? sh.fh[yi + 1] : FH_NONE;
+        const uint64_t Dend = (x < C) ? sh.dp[xi + 1] : sh.dp[xi];
         const int m = nlc + nhc;
         if (m > 0) {
             const int d0 = (int)(((int64_t)m * threadIdx.x) / TPB);
@@ -680,11 +764,10 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                     const bool take_h = (j < nhc) && (i >= nlc || B.key[offB + ph + j] <= A.key[pl + i]);
                     if (take_h) {
                         const int hp = offB + ph + j;
-                        const u128 E = B.key[hp];
-                        const u128 Dn = (pl + i < nlx) ? A.key[pl + i] : Dend;
-                        const i128 num = (i128)Q + (i128)E - (i128)Dn;
-                        float t = (float)(u128_to_double((u128)(num > 0 ? num : 0)) * sc.rQ);
-                        t = fminf(t, 1.0f);
+                        const uint64_t E = B.key[hp];
+                        const uint64_t Dn = (pl + i < nlx) ? A.key[pl + i] : Dend;
+                        float t = (float)(1.0 + (double)(int64_t)(E - Dn) * tscale);
+                        t = fminf(fmaxf(t, 0.0f), 1.0f);
                         const int32_t own = B.idx[hp];
                         const int32_t al = (ph + j + 1 < nhy) ? B.idx[hp + 1] : (nextH != FH_NONE ? nextH : own);
                         store_entry(J.table, own, t, al);
@@ -713,23 +796,22 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
         if (heavy_ev) {
             ++y;
             ph = 0;
-            if (y == x) {
+            if (reuse) {
                 sb = sa;
             } else {
                 sb = 1 - sa;
-                load_pack_tile(sh.slot[sb], y, J, sc, sh.tmp);
+                if (need) fill_tile(sh.slot[sb], y, vn, J, sc, sh.tmp);
             }
         } else {
             ++x;
             pl = 0;
-            if (x == y) {
+            if (reuse) {
                 sa = sb;
             } else {
                 sa = 1 - sb;
-                load_pack_tile(sh.slot[sa], x, J, sc, sh.tmp);
+                if (need) fill_tile(sh.slot[sa], x, vn, J, sc, sh.tmp);
             }
         }
-        __syncthreads();
     }
 }
 
@@ -779,6 +861,17 @@ __global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
+void phase_blocks(const JobDesc& J, int64_t b[PH_COUNT]) {
+    b[PH_RED] = J.nred;
+    b[PH_FIN] = 1;
+    b[PH_TILE] = cdiv(J.ntiles, TILES_PER_AGG_BLOCK);
+    b[PH_SEG] = J.nseg;
+    b[PH_TOP] = 1;
+    b[PH_SPLIT] = cdiv(J.npack, TPB);
+    b[PH_PACK] = J.npack;
+    b[PH_SAMPLE] = cdiv(J.k, SAMPLES_PER_BLOCK);
+}
+
 hipError_t launch_build(const JobTable& jt0, const int64_t* blocks, hipStream_t st) {
     JobTable jt = jt0;
 #define WRS_LAUNCH(kern, ph)                                                       \
@@ -796,6 +889,7 @@ hipError_t launch_build(const JobTable& jt0, const int64_t* blocks, hipStream_t 
     WRS_LAUNCH(k_scan_seg, PH_SEG);
     WRS_LAUNCH(k_scan_top, PH_TOP);
     WRS_LAUNCH(k_scan_fix, PH_SEG);
+    WRS_LAUNCH(k_split, PH_SPLIT);
     WRS_LAUNCH(k_pack, PH_PACK);
 #undef WRS_LAUNCH
     return hipSuccess;

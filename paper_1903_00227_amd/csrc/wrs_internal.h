@@ -13,6 +13,7 @@ typedef __int128 i128;
 // Launch geometry.  Every size below is a constant, so a table's result depends
 // on its own n only (never on how jobs are batched).
 constexpr int TILE = 1024;          // items per tile (classification and prefix sums)
+constexpr int TILES_PER_AGG_BLOCK = 4;  // tile aggregation: one wave per tile
 constexpr int TPB = 256;            // threads per block of the tile kernels
 constexpr int IPT = TILE / TPB;     // items per thread in a tile
 constexpr int PACK_STEPS = 16;      // coarse tile events per pack block
@@ -34,6 +35,9 @@ struct alignas(16) BuildScalars {
     double nscale;    // n * 2^-G
     uint64_t Qn;      // floor(Q / n): item i is light iff q_i <= Qn
     int64_t npos;     // number of positive weights
+    int32_t kshift;   // merge keys are prefix sums >> kshift (64-bit)
+    int32_t pad2;
+    double tscale;    // 2^kshift / Q: key difference -> bucket fraction
 };
 
 // Everything one table needs on the device.
@@ -55,14 +59,18 @@ struct JobDesc {
     uint32_t* NL;         // [C+1] lights before tile c
     u128* DP;             // [C+1] light deficit before tile c
     u128* EP;             // [C+1] heavy excess before tile c
+    uint64_t* DP64;       // [C+1] DP >> kshift (merge keys)
+    uint64_t* EP64;       // [C+1] EP >> kshift
     int32_t* FH;          // [C+1] first heavy item in tiles >= c, -1 if none
+    int32_t* pstart;      // [npack] light events before each pack block's first event
+    int32_t npack;        // pack blocks
     uint32_t* sNL;        // [nseg+1] segment totals / prefixes of the tile scan
     u128* sDP;
     u128* sEP;
     int32_t* sFH;
 };
 
-enum Phase { PH_RED = 0, PH_FIN, PH_TILE, PH_SEG, PH_TOP, PH_PACK, PH_SAMPLE, PH_COUNT };
+enum Phase { PH_RED = 0, PH_FIN, PH_TILE, PH_SEG, PH_TOP, PH_SPLIT, PH_PACK, PH_SAMPLE, PH_COUNT };
 
 // A launch covers one phase of one job (jobs == nullptr, description in `one`)
 // or of many jobs (device array `jobs`, with block offsets per phase in
@@ -78,6 +86,9 @@ struct JobTable {
 // Byte size of the per-table workspace and the pointer layout inside it.
 size_t build_ws_bytes(int64_t n);
 void build_ws_layout(JobDesc& J, void* ws, int64_t n);
+
+// Blocks of every phase for one table (depends on n and k only).
+void phase_blocks(const JobDesc& J, int64_t blocks[PH_COUNT]);
 
 // Host launchers (stream-ordered).
 hipError_t launch_build(const JobTable& jt, const int64_t* blocks, hipStream_t st);

@@ -297,7 +297,8 @@ static bool issue(Server& S) {
             d[j].k = 0;
             build_ws_layout(d[j], scratch[wsi++].first, tb->n);
             d[j].sc = tb->sc;
-            int64_t b[PH_COUNT] = {d[j].nred, 1, d[j].ntiles, d[j].nseg, 1, cdiv(2 * (int64_t)d[j].ntiles, PACK_STEPS), 0};
+            int64_t b[PH_COUNT];
+            phase_blocks(d[j], b);
             for (int p = 0; p < PH_COUNT; ++p) off[(size_t)p * (nb + 1) + j + 1] = off[(size_t)p * (nb + 1) + j] + b[p];
         }
         char* h = S.staging[slot];
