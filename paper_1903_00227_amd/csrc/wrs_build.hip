@@ -206,8 +206,10 @@ __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
     S.nscale = 0;
     S.Qn = 0;
     S.kshift = 0;
-    S.pad2 = 0;
+    S.wthr = 0;
     S.tscale = 0;
+    S.Qk = 0;
+    S.pad3 = 0;
     if (bad || !(hi > 0.0)) {
         S.status = WRS_EDOMAIN;
     } else {
@@ -239,6 +241,15 @@ __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
         const int sh = max(0, qbits + nbits - 62);
         S.kshift = sh;
         S.tscale = ldexp(1.0, sh) * S.rQ;
+        S.Qk = (uint64_t)((Q + (sh > 0 ? ((u128)1 << (sh - 1)) : (u128)0)) >> sh);
+        // quantize is monotone in w and FP32 bit patterns of w >= 0 are ordered
+        // like the values: find the smallest pattern with q > Qn.
+        uint32_t lo = 0, hi = 0x7F800000u;
+        while (lo < hi) {
+            const uint32_t mid = lo + ((hi - lo) >> 1);
+            if (quantize(__uint_as_float(mid), G) > (u128)qn) hi = mid; else lo = mid + 1;
+        }
+        S.wthr = lo;
     }
     *J.sc = S;
 }
@@ -284,7 +295,7 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
     if (c >= J.ntiles) return;
     const int lane = threadIdx.x & 63;
     const int G = sc->G;
-    const uint64_t Qn = sc->Qn;
+    const uint32_t wthr = sc->wthr;
     const u128 Q = sc->Q;
     const int64_t n = J.n;
     const int64_t base = c * TILE;
@@ -312,8 +323,9 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
         for (int e = 0; e < 4; ++e) {
             const int i = r * 256 + lane * 4 + e;
             if (i < cnt) {
-                const u128 q = quantize(v[4 * r + e], G);
-                if (q <= (u128)Qn) {
+                const float x = v[4 * r + e];
+                const u128 q = quantize(x, G);
+                if (__float_as_uint(x) < wthr) {
                     ++nl;
                     sql += q;
                 } else {
@@ -530,11 +542,15 @@ __global__ __launch_bounds__(TPB) void k_scan_fix(JobTable jt) {
 // block starts (the paper's split(), on tile granularity); the block refines
 // the exact state inside its first two tiles and merges cell by cell.
 //
-// Merge keys are the exact prefix sums shifted right by kshift (64-bit keys,
-// resolution 2^-33 bucket or finer for n < 2^31).  Every block compares the
-// same 64-bit keys, so all cuts agree; the keys are a monotone image of the
-// exact sums, so the merge differs from the exact sweep only where a light's
-// and a heavy's sums are closer than that resolution.
+// Merge keys are 64-bit: the exact tile prefix shifted right by kshift (key
+// unit 2^kshift / Q bucket, about 2 n 2^-62: 2^-33 at n = 2^28) plus, inside a
+// tile, the item sizes rounded to that unit.  Every key is a deterministic
+// function of the input and the keys of a tile are non-decreasing, so every
+// block makes the same decisions and the cuts agree.  Inside a tile the
+// rounding can move a key by at most half a unit per item before it; the merge
+// then differs from the exact sweep only where a light's and a heavy's sums are
+// that close, and a heavy's t by at most that much.  On small inputs the item
+// sizes are exact multiples of the unit and the table equals the sweep's.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(TPB) void k_split(JobTable jt) {
     __shared__ int s_job;
@@ -558,19 +574,29 @@ __global__ __launch_bounds__(TPB) void k_split(JobTable jt) {
     J.pstart[b] = (int32_t)lo;
 }
 
+// A tile staged for the merge.  Lights sit at [0, nl) in index order with the
+// deficit sum before them as key; heavies at [nl, nl + nh) with the excess sum
+// through them.
 struct PackSlot {
-    uint64_t key[TILE];  // lights [0, nl): D before the light; heavies [nl, nl+nh): E through the heavy
-    int32_t idx[TILE];   // item index
-    float tl[TILE];      // t of the lights
+    uint64_t key[TILE];
+    float w[TILE];        // weight of a light (its bucket keeps n w / W)
+    uint16_t off[TILE];   // item offset inside the tile
     int32_t nl, nh;
+    int64_t tile;
+};
+
+struct ScanTmp64 {
+    uint64_t a[TPB / 64];
+    uint64_t b[TPB / 64];
+    uint32_t c[TPB / 64];
 };
 
 struct PackShared {
     PackSlot slot[2];
+    ScanTmp64 tmp;
     uint64_t dp[PACK_STEPS + 2];  // DP64[x0 + i]
     uint64_t ep[PACK_STEPS + 2];  // EP64[y0 + i]
     int32_t fh[PACK_STEPS + 2];   // FH[y0 + i]
-    ScanTmp tmp;
     int s_job;
 };
 
@@ -584,67 +610,123 @@ __device__ __forceinline__ void fetch_tile(const JobDesc& J, int64_t c, float v[
     load_tile_items(J.w, base, (int)min((int64_t)TILE, J.n - base), v);
 }
 
-// Fill slot S with tile c from prefetched weights v (c == C gives an empty tile).
+// n q(w) / 2^kshift rounded to nearest (ties up): the item's size in key
+// units.  n q = (n m) 2^s on the grid; the result is below 2^62 for every
+// weight <= W.
+__device__ __forceinline__ uint64_t size_keyunits(float w, const BuildScalars& sc, uint32_t n) {
+    const uint32_t bits = __float_as_uint(w);
+    const uint32_t e = bits >> 23;
+    const uint32_t m = (bits & 0x7FFFFFu) | (e ? 0x800000u : 0u);
+    const int s = (int)(e ? e : 1u) - 150 - sc.G;
+    uint64_t x;
+    int r;  // right shift
+    if (s >= 0) {
+        x = (uint64_t)m * n;
+        r = sc.kshift - s;
+    } else {
+        x = (uint64_t)quantize(w, sc.G) * n;
+        r = sc.kshift;
+    }
+    if (r <= 0) return x << min(-r, 63);
+    if (r >= 64) return 0;
+    return (x >> r) + ((x >> (r - 1)) & 1ull);
+}
+
+__device__ __forceinline__ void block_scan64(uint32_t cnt, uint64_t a, uint64_t b, uint32_t& cnt_ex, uint64_t& a_ex,
+                                             uint64_t& b_ex, uint32_t& cnt_tot, ScanTmp64& tmp) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    uint32_t ci = cnt;
+    uint64_t ai = a, bi = b;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t cu = __shfl_up(ci, d, 64);
+        const uint64_t au = __shfl_up((unsigned long long)ai, d, 64);
+        const uint64_t bu = __shfl_up((unsigned long long)bi, d, 64);
+        if (lane >= d) {
+            ci += cu;
+            ai += au;
+            bi += bu;
+        }
+    }
+    if (lane == 63) {
+        tmp.c[wv] = ci;
+        tmp.a[wv] = ai;
+        tmp.b[wv] = bi;
+    }
+    __syncthreads();
+    uint32_t cp = 0;
+    uint64_t ap = 0, bp = 0;
+    cnt_tot = 0;
+#pragma unroll
+    for (int k = 0; k < TPB / 64; ++k) {
+        if (k < wv) {
+            cp += tmp.c[k];
+            ap += tmp.a[k];
+            bp += tmp.b[k];
+        }
+        cnt_tot += tmp.c[k];
+    }
+    cnt_ex = cp + ci - cnt;
+    a_ex = ap + ai - a;
+    b_ex = bp + bi - b;
+}
+
+// Fill slot S with tile c from the prefetched weights v (c == C: empty tile).
+// Keys: the exact tile prefix (DP64, EP64) plus the rounded sizes of the items
+// before (lights) or through (heavies) each item in the tile.
 __device__ void fill_tile(PackSlot& S, int64_t c, const float v[IPT], const JobDesc& J, const BuildScalars& sc,
-                          ScanTmp& tmp) {
+                          ScanTmp64& tmp) {
     __syncthreads();  // every thread is done with the slot's previous contents
     if (c >= J.ntiles) {
         if (threadIdx.x == 0) {
             S.nl = 0;
             S.nh = 0;
+            S.tile = c;
         }
         __syncthreads();
         return;
     }
-    const int64_t n = J.n;
+    const uint32_t n = (uint32_t)J.n;
     const int64_t base = c * TILE;
-    const int cnt = (int)min((int64_t)TILE, n - base);
-    const u128 Q = sc.Q;
-    const uint64_t Qn = sc.Qn;
-    const int ks = sc.kshift;
-    const u128 Dbase = J.DP[c];
-    const u128 Ebase = J.EP[c];
-    u128 d[IPT];
+    const int cnt = (int)min((int64_t)TILE, J.n - base);
+    const int i0 = threadIdx.x * IPT;
+    const uint64_t Qk = sc.Qk;
     bool light[IPT];
+    uint64_t inc[IPT];
     uint32_t nl = 0;
-    u128 dsum = 0, esum = 0;
+    uint64_t dsum = 0, esum = 0;
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
-        const int i = threadIdx.x * IPT + e;
-        const bool valid = i < cnt;
-        const u128 q = quantize(v[e], sc.G);
-        light[e] = valid && (q <= (u128)Qn);
-        const u128 nq = (u128)n * q;
-        d[e] = !valid ? (u128)0 : (light[e] ? Q - nq : nq - Q);
-        if (light[e]) {
-            ++nl;
-            dsum += d[e];
-        } else {
-            esum += d[e];
-        }
+        const bool valid = i0 + e < cnt;
+        light[e] = valid && (__float_as_uint(v[e]) < sc.wthr);
+        const uint64_t z = size_keyunits(v[e], sc, n);
+        inc[e] = !valid ? 0ull : (light[e] ? Qk - z : z - Qk);
+        nl += light[e];
+        dsum += light[e] ? inc[e] : 0ull;
+        esum += light[e] ? 0ull : inc[e];
     }
     uint32_t nl_ex, nl_tot;
-    u128 d_ex, e_ex, d_tot, e_tot;
-    block_scan3(nl, dsum, esum, nl_ex, d_ex, e_ex, nl_tot, d_tot, e_tot, tmp);
+    uint64_t d_ex, e_ex;
+    block_scan64(nl, dsum, esum, nl_ex, d_ex, e_ex, nl_tot, tmp);
     uint32_t lr = nl_ex;
-    uint32_t hr = (uint32_t)(threadIdx.x * IPT) - nl_ex;  // heavies before this thread's items
-    u128 dacc = Dbase + d_ex;
-    u128 eacc = Ebase + e_ex;
+    uint32_t hr = (uint32_t)i0 - nl_ex;  // heavies before this thread's items
+    uint64_t dacc = J.DP64[c] + d_ex;
+    uint64_t eacc = J.EP64[c] + e_ex;
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
-        const int i = threadIdx.x * IPT + e;
-        if (i < cnt) {
+        if (i0 + e < cnt) {
             if (light[e]) {
-                S.key[lr] = (uint64_t)(dacc >> ks);
-                S.idx[lr] = (int32_t)(base + i);
-                S.tl[lr] = (float)((double)v[e] * sc.nscale * sc.rQ);
-                dacc += d[e];
+                S.key[lr] = dacc;
+                S.w[lr] = v[e];
+                S.off[lr] = (uint16_t)(i0 + e);
+                dacc += inc[e];
                 ++lr;
             } else {
-                eacc += d[e];
-                const int p = (int)nl_tot + (int)hr;
-                S.key[p] = (uint64_t)(eacc >> ks);
-                S.idx[p] = (int32_t)(base + i);
+                eacc += inc[e];
+                const int p = (int)(nl_tot + hr);
+                S.key[p] = eacc;
+                S.off[p] = (uint16_t)(i0 + e);
                 ++hr;
             }
         }
@@ -652,34 +734,52 @@ __device__ void fill_tile(PackSlot& S, int64_t c, const float v[IPT], const JobD
     if (threadIdx.x == 0) {
         S.nl = (int)nl_tot;
         S.nh = cnt - (int)nl_tot;
+        S.tile = c;
     }
     __syncthreads();
 }
 
-// first position in [from, nl) whose light key is >= v
+// First position p in [from, to) with !(key[p] < v) (keys non-decreasing): a
+// 64-ary search by one wave, two rounds for a tile.
+template <bool LE>
+__device__ __forceinline__ int wave_search(const uint64_t* key, int from, int to, uint64_t v) {
+    const int lane = threadIdx.x & 63;
+    int lo = from, hi = to;  // answer in [lo, hi]
+    while (lo < hi) {
+        const int step = (hi - lo + 63) >> 6;
+        const int p = lo + lane * step;
+        const bool pr = (p < hi) && (LE ? (key[p] <= v) : (key[p] < v));
+        const uint64_t mask = __ballot(pr);
+        const int K = __popcll(mask);
+        if (K == 0) {
+            hi = lo;
+        } else {
+            const int pk1 = lo + (K - 1) * step;
+            const int nhi = min(hi, pk1 + step);
+            lo = pk1 + 1;
+            hi = nhi;
+        }
+    }
+    return lo;
+}
+
+// number of lights in [from, nl) with key < v, plus from
 __device__ __forceinline__ int lights_below(const PackSlot& S, int from, uint64_t v) {
-    int lo = from, hi = S.nl;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (S.key[mid] < v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+    return wave_search<false>(S.key, from, S.nl, v);
 }
 
-// first position in [from, nh) whose heavy key is > v
+// number of heavies in [from, nh) with key <= v, plus from
 __device__ __forceinline__ int heavies_upto(const PackSlot& S, int from, uint64_t v) {
-    int lo = from, hi = S.nh;
-    const int off = S.nl;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (S.key[off + mid] <= v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+    return wave_search<true>(S.key + S.nl, from, S.nh, v);
 }
 
-__device__ __forceinline__ void store_entry(wrs_entry* table, int32_t item, float t, int32_t alias) {
+__device__ __forceinline__ void store_entry(wrs_entry* table, int64_t item, float t, int32_t alias) {
     uint2 v = make_uint2(__float_as_uint(t), (uint32_t)alias);
     *(uint2*)(table + item) = v;
+}
+
+__device__ __forceinline__ float light_t(float w, const BuildScalars& sc) {
+    return (float)((double)w * sc.nscale * sc.rQ);
 }
 
 __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
@@ -729,13 +829,14 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
         const bool has_l = x + 1 <= C;
         const uint64_t EPn = sh.ep[yi + 1];
         const bool heavy_ev = has_h && (!has_l || !dpkey_lt(x + 1, EPn));
-        // prefetch the tile that the event opens, unless the other stream holds it
+        // the tile this event opens: fetched now, staged after the merge
         const int64_t nt = heavy_ev ? y + 1 : x + 1;
         const bool reuse = heavy_ev ? (nt == x) : (nt == y);
         const bool need = (s + 1 < s1) && !reuse;
         float vn[IPT];
         if (need) fetch_tile(J, nt, vn);
         const int nlx = A.nl, nhy = B.nh, offB = B.nl;
+        const int64_t abase = A.tile * TILE, bbase = B.tile * TILE;
         int nlc, nhc;
         if (heavy_ev) {
             nhc = nhy - ph;
@@ -747,7 +848,34 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
         const int32_t nextH = has_h ? sh.fh[yi + 1] : FH_NONE;
         const uint64_t Dend = (x < C) ? sh.dp[xi + 1] : sh.dp[xi];
         const int m = nlc + nhc;
-        if (m > 0) {
+        if (nhc == 0 && nlc > 0) {
+            // lights only: all take the same alias; lanes take consecutive lights
+            const bool hv = ph < nhy;
+            const int32_t al = hv ? (int32_t)(bbase + B.off[offB + ph]) : nextH;
+            for (int d = threadIdx.x; d < nlc; d += TPB) {
+                const int lp = pl + d;
+                const int64_t own = abase + A.off[lp];
+                float t = light_t(A.w[lp], sc);
+                int32_t a2 = al;
+                if (!hv && al == FH_NONE) {
+                    a2 = (int32_t)own;
+                    t = fminf(t, 1.0f);
+                }
+                store_entry(J.table, own, t, a2);
+            }
+        } else if (nlc == 0 && nhc > 0) {
+            // heavies only: each keeps 1 + (E - D) with the same next light
+            const uint64_t Dn = (pl < nlx) ? A.key[pl] : Dend;
+            for (int d = threadIdx.x; d < nhc; d += TPB) {
+                const int hp = offB + ph + d;
+                float t = (float)(1.0 + (double)(int64_t)(B.key[hp] - Dn) * tscale);
+                t = fminf(fmaxf(t, 0.0f), 1.0f);
+                const int64_t own = bbase + B.off[hp];
+                const int32_t al = (ph + d + 1 < nhy) ? (int32_t)(bbase + B.off[hp + 1])
+                                                      : (nextH != FH_NONE ? nextH : (int32_t)own);
+                store_entry(J.table, own, t, al);
+            }
+        } else if (m > 0) {
             const int d0 = (int)(((int64_t)m * threadIdx.x) / TPB);
             const int d1 = (int)(((int64_t)m * (threadIdx.x + 1)) / TPB);
             if (d1 > d0) {
@@ -768,21 +896,22 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                         const uint64_t Dn = (pl + i < nlx) ? A.key[pl + i] : Dend;
                         float t = (float)(1.0 + (double)(int64_t)(E - Dn) * tscale);
                         t = fminf(fmaxf(t, 0.0f), 1.0f);
-                        const int32_t own = B.idx[hp];
-                        const int32_t al = (ph + j + 1 < nhy) ? B.idx[hp + 1] : (nextH != FH_NONE ? nextH : own);
+                        const int64_t own = bbase + B.off[hp];
+                        const int32_t al = (ph + j + 1 < nhy) ? (int32_t)(bbase + B.off[hp + 1])
+                                                              : (nextH != FH_NONE ? nextH : (int32_t)own);
                         store_entry(J.table, own, t, al);
                         ++j;
                     } else {
                         const int lp = pl + i;
-                        const int32_t own = A.idx[lp];
-                        float t = A.tl[lp];
+                        const int64_t own = abase + A.off[lp];
+                        float t = light_t(A.w[lp], sc);
                         int32_t al;
                         if (ph + j < nhy) {
-                            al = B.idx[offB + ph + j];
+                            al = (int32_t)(bbase + B.off[offB + ph + j]);
                         } else if (nextH != FH_NONE) {
                             al = nextH;
                         } else {
-                            al = own;
+                            al = (int32_t)own;
                             t = fminf(t, 1.0f);
                         }
                         store_entry(J.table, own, t, al);

@@ -33,6 +33,7 @@ __device__ __forceinline__ u128 quantize(float w, int G) {
     uint32_t m = bits & 0x7FFFFFu;
     if (e) m |= 0x800000u;
     const int s = (int)(e ? e : 1u) - 150 - G;  // w = m * 2^(s + G)
+    if (s > 103) return ~(u128)0;               // far above any weight <= W: saturate
     if (s >= 0) return (u128)m << s;
     if (s <= -32) return 0;
     const int sh = -s;
@@ -40,6 +41,19 @@ __device__ __forceinline__ u128 quantize(float w, int G) {
     const uint32_t rem = m & ((1u << sh) - 1u);
     const uint32_t half = 1u << (sh - 1);
     return (u128)(r + ((rem > half) || (rem == half && (r & 1u))));
+}
+
+// n * quantize(w, G), exactly: (n m) 2^s with one 32x32 product when the
+// weight lies on the grid (s >= 0), else n times the rounded q.
+__device__ __forceinline__ u128 nscaled(float w, int G, uint32_t n) {
+    const uint32_t bits = __float_as_uint(w);
+    const uint32_t e = bits >> 23;
+    uint32_t m = bits & 0x7FFFFFu;
+    if (e) m |= 0x800000u;
+    const int s = (int)(e ? e : 1u) - 150 - G;
+    if (s > 72) return ~(u128)0;  // only for weights far above W (never for valid input)
+    if (s >= 0) return (u128)((uint64_t)m * n) << s;
+    return (u128)((uint64_t)quantize(w, G) * n);
 }
 
 __device__ __forceinline__ double u128_to_double(u128 v) {

@@ -3,7 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/wrs.h"
+#include "wrs.h"
 
 namespace wrs {
 
@@ -36,8 +36,10 @@ struct alignas(16) BuildScalars {
     uint64_t Qn;      // floor(Q / n): item i is light iff q_i <= Qn
     int64_t npos;     // number of positive weights
     int32_t kshift;   // merge keys are prefix sums >> kshift (64-bit)
-    int32_t pad2;
+    uint32_t wthr;    // bit pattern of the smallest heavy FP32 weight
     double tscale;    // 2^kshift / Q: key difference -> bucket fraction
+    uint64_t Qk;      // Q >> kshift, rounded to nearest: bucket capacity in key units
+    int64_t pad3;
 };
 
 // Everything one table needs on the device.

@@ -1,10 +1,13 @@
 """GPU parity of alias-table construction (C ABI wrs_alias_build) against the oracle.
 
 Bar: aliases bit-identical to the exact sequential sweep (Algorithm 2,
-Section 4.1), thresholds within 1 FP32 ulp of its correctly rounded values (the
-kernel rounds an exact integer ratio through FP64, at most 4 FP64 roundings, so
-it can differ from correct rounding only within 2^-51 relative of an FP32
-midpoint), and every item's mass within 1e-6 relative of n w_i / W.
+Section 4.1); every item's mass within 1e-6 relative of n w_i / W; thresholds
+within the error the kernel's arithmetic allows:
+  * a light bucket's t = n w / W goes through two FP64 products before the FP32
+    rounding, so it is within 1 ulp of the correctly rounded value;
+  * a heavy bucket's t = 1 + (E - D) / W uses 64-bit merge keys: exact tile
+    prefix sums plus item sizes rounded to the key unit u <= 2^(floor(log2 n) - 60)
+    bucket, so E - D is off by at most (TILE/2 + 1) u, TILE = 1024, plus 1 ulp.
 """
 import numpy as np
 import pytest
@@ -26,12 +29,21 @@ FAMILIES = ["uniform", "power0.5", "power1", "power2", "ints", "equal", "one", "
             "tiny_heavies"]
 
 
+def t_tolerance(n, t_ref):
+    unit = 2.0 ** (int(n).bit_length() - 1 - 60)
+    ulp = np.spacing(np.abs(t_ref).astype(np.float32)).astype(np.float64)
+    return ulp + 513 * unit
+
+
 def check_against_sweep(orc, w, t, a):
     t_ref, a_ref = orc.sweep_build(w)
     bad = np.nonzero(a != a_ref)[0]
     assert bad.size == 0, f"{bad.size} alias mismatches, first at {bad[:5]}: gpu {a[bad[:5]]} ref {a_ref[bad[:5]]}"
-    ud = ulp_diff(t, t_ref)
-    assert ud.max() <= 1, f"threshold off by {ud.max()} ulp at {np.argmax(ud)}"
+    dt = np.abs(t.astype(np.float64) - t_ref.astype(np.float64))
+    tol = t_tolerance(w.size, t_ref)
+    assert np.all(dt <= tol), f"threshold off by {dt.max()} at {np.argmax(dt - tol)}"
+    light = w.astype(np.float64) * w.size <= w.astype(np.float64).sum() * (1 - 1e-12)
+    assert ulp_diff(t[light], t_ref[light]).max(initial=0) <= 1
     mass, err = orc.reconstruct(w, t, a)
     pos = w > 0
     if pos.any():
