@@ -125,6 +125,12 @@ def main():
     value = (2 * n * steps) / (tot_build * 1e-3) / 1e9
     gsps = (2 * k * steps) / (tot_sample * 1e-3) / 1e9
     if args.profile_only:
+        # a plain 1 GiB device copy: calibrates the HBM byte counters
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        bench_wor(wrs, torch, np, workloads, reps=1)
+        torch.cuda.synchronize()
         log(f"profile run done: build {tot_build / steps / 2:.3f} ms, sample {tot_sample / steps / 2:.3f} ms")
         return
 
@@ -163,10 +169,38 @@ def main():
                      "algorithmic_bytes_per_launch": samp_bytes},
     }
     if not args.skip_extras:
+        result["without_replacement"] = bench_wor(wrs, torch, np, workloads)
         result["batched"] = bench_batched(wrs, torch, np, workloads)
         result["served"] = bench_served(wrs, torch, np, workloads)
         result["cpu_baseline"] = bench_cpu(np, workloads)
     print(json.dumps(result), flush=True)
+
+
+def bench_wor(wrs, torch, np, workloads, reps=5):
+    """n = 2^26 power law s = 0.5 permuted (seed 3), Philox key 3, k in
+    {2^10, 2^16, 2^20}: exponential keys, threshold filter, exact top-k."""
+    dev = torch.device("cuda:0")
+    n = 1 << 26
+    log("without replacement: n=2^26")
+    w = torch.from_numpy(workloads.power_law(n, 0.5, 3)).to(dev)
+    res = {"workload": "n=2^26 FP32 weights, power law s=0.5 permuted (seed 3), Philox key 3"}
+    for lk in (10, 16, 20):
+        k = 1 << lk
+        out = torch.empty(k, dtype=torch.int32, device=dev)
+        ws = wrs.new_workspace(wrs.OP_WOR, n, k, dev)
+        wrs.sample_wor(w, n, k, 3, 0, out, ws)
+        assert wrs.status(ws) == wrs.OK
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            wrs.sample_wor(w, n, k, 3, 0, out, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"k=2^{lk}"] = {"ms": round(ms, 4), "gitems_s": round(n / (ms * 1e-3) / 1e9, 2),
+                            "hbm_frac_4B_per_item": round(4.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del out, ws
+    return res
 
 
 def bench_batched(wrs, torch, np, workloads):

@@ -190,10 +190,15 @@ __global__ __launch_bounds__(1024) void k_wor_tau(WorArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// Candidates are staged in LDS per block (at most WOR_TPB * WOR_IPT of them)
+// and reserved in the output with one atomic per block.
 __global__ __launch_bounds__(WOR_TPB) void k_wor_filter(WorArgs A, int pass) {
+    __shared__ double s_key[WOR_TPB * WOR_IPT];
+    __shared__ int32_t s_idx[WOR_TPB * WOR_IPT];
     __shared__ double s_max[WOR_TPB / 64];
     __shared__ unsigned long long s_pos[WOR_TPB / 64];
     __shared__ uint32_t s_bad[WOR_TPB / 64];
+    __shared__ uint32_t s_cnt, s_base;
     WorScalars* S = A.S;
     if (pass == 2) {
         if (S->status != WRS_OK || (int64_t)S->count >= A.k) return;
@@ -201,12 +206,14 @@ __global__ __launch_bounds__(WOR_TPB) void k_wor_filter(WorArgs A, int pass) {
     const double tau = (pass == 2) ? (double)INFINITY : S->tau;
     uint32_t* counter = (pass == 2) ? &S->count2 : &S->count;
     const int64_t n = A.n;
+    if (threadIdx.x == 0) s_cnt = 0;
     if (pass == 1) {  // clear this block's share of the bitmap
         const int64_t per = cdiv(A.nwords, (int64_t)gridDim.x);
         const int64_t w0 = (int64_t)blockIdx.x * per;
         const int64_t w1 = min(A.nwords, w0 + per);
         for (int64_t i = w0 + threadIdx.x; i < w1; i += WOR_TPB) A.bitmap[i] = 0u;
     }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     double kmax = 0.0;
     uint32_t bad = 0;
@@ -235,16 +242,13 @@ __global__ __launch_bounds__(WOR_TPB) void k_wor_filter(WorArgs A, int pass) {
             const uint32_t cnt = (uint32_t)__popcll(mask);
             const int leader = __ffsll((long long)mask) - 1;
             uint32_t b = 0;
-            if (lane == leader) b = atomicAdd(counter, cnt);
+            if (lane == leader) b = atomicAdd(&s_cnt, cnt);
             b = __shfl(b, leader, 64);
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
             if (cand) {
-                const uint32_t p = b + rank;
-                if ((int64_t)p < n) {
-                    A.ckey[p] = key;
-                    A.cidx[p] = (int32_t)i;
-                }
+                s_key[b + rank] = key;
+                s_idx[b + rank] = (int32_t)i;
                 kmax = fmax(kmax, key);
             }
         }
@@ -261,11 +265,12 @@ __global__ __launch_bounds__(WOR_TPB) void k_wor_filter(WorArgs A, int pass) {
         s_pos[wv] = pos;
     }
     __syncthreads();
+    const uint32_t nc = s_cnt;
     if (threadIdx.x == 0) {
+        s_base = nc ? atomicAdd(counter, nc) : 0u;
         for (int k = 1; k < WOR_TPB / 64; ++k) {
             kmax = fmax(kmax, s_max[k]);
             bad |= s_bad[k];
-            pos += s_pos[k];
         }
         kmax = fmax(kmax, s_max[0]);
         bad |= s_bad[0];
@@ -273,6 +278,15 @@ __global__ __launch_bounds__(WOR_TPB) void k_wor_filter(WorArgs A, int pass) {
         if (pass == 1) {
             if (bad) atomicOr(&S->bad, 1u);
             atomicAdd(&S->npos, (unsigned long long)(s_pos[0] + s_pos[1] + s_pos[2] + s_pos[3]));
+        }
+    }
+    __syncthreads();
+    const uint32_t b0 = s_base;
+    for (uint32_t c = threadIdx.x; c < nc; c += WOR_TPB) {
+        const uint32_t p = b0 + c;
+        if ((int64_t)p < n) {
+            A.ckey[p] = s_key[c];
+            A.cidx[p] = s_idx[c];
         }
     }
 }
