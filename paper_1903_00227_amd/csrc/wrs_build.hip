@@ -259,12 +259,15 @@ __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void load_tile_items(const float* w, int64_t base, int cnt, float v[IPT]) {
     const int i0 = threadIdx.x * IPT;
-    if (i0 + IPT <= cnt && ((((uintptr_t)(w + base + i0)) & 15) == 0)) {
-        const float4 x = *(const float4*)(w + base + i0);
-        v[0] = x.x;
-        v[1] = x.y;
-        v[2] = x.z;
-        v[3] = x.w;
+    if ((IPT % 4) == 0 && i0 + IPT <= cnt && ((((uintptr_t)(w + base + i0)) & 15) == 0)) {
+#pragma unroll
+        for (int r = 0; r < IPT / 4; ++r) {
+            const float4 x = *(const float4*)(w + base + i0 + 4 * r);
+            v[4 * r] = x.x;
+            v[4 * r + 1] = x.y;
+            v[4 * r + 2] = x.z;
+            v[4 * r + 3] = x.w;
+        }
     } else {
 #pragma unroll
         for (int e = 0; e < IPT; ++e) v[e] = (i0 + e < cnt) ? w[base + i0 + e] : 0.0f;
@@ -974,7 +977,7 @@ __global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
 #pragma unroll
     for (int e = 0; e < SAMPLE_UNROLL; ++e) {
         const int64_t s = s0 + (int64_t)e * SAMPLE_TPB;
-        ent[e] = (s < k) ? __builtin_nontemporal_load(table + r[e]) : 0ull;
+        ent[e] = (s < k) ? table[r[e]] : 0ull;  // cached: small tables stay in L2 / MALL
     }
 #pragma unroll
     for (int e = 0; e < SAMPLE_UNROLL; ++e) {
