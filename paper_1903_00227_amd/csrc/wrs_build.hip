@@ -139,17 +139,17 @@ __global__ __launch_bounds__(TPB) void k_reduce(JobTable jt) {
     __shared__ double s_hi[TPB / 64], s_lo[TPB / 64];
     __shared__ uint32_t s_bad[TPB / 64], s_pos[TPB / 64];
     int64_t lb;
-    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
     const int64_t base = lb * RED_CHUNK;
     const int64_t end = min(base + (int64_t)RED_CHUNK, J.n);
-    const float* w = J.w;
+    const WRS_GLOBAL float* w = glb(J.w);
     double hi = 0.0, lo = 0.0;
     uint32_t bad = 0, pos = 0;
     if ((((uintptr_t)(w + base)) & 15) == 0) {
         const int64_t nv = (end - base) >> 2;
-        const float4* w4 = (const float4*)(w + base);
+        const WRS_GLOBAL vfloat4* w4 = (const WRS_GLOBAL vfloat4*)(w + base);
         for (int64_t g = threadIdx.x; g < nv; g += TPB) {
-            const float4 v = w4[g];
+            const vfloat4 v = w4[g];
             red_item(v.x, hi, lo, bad, pos);
             red_item(v.y, hi, lo, bad, pos);
             red_item(v.z, hi, lo, bad, pos);
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
     __shared__ double s_hi[TPB / 64], s_lo[TPB / 64];
     __shared__ uint32_t s_bad[TPB / 64], s_pos[TPB / 64];
     int64_t lb;
-    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
     double hi = 0.0, lo = 0.0;
     uint32_t bad = 0, pos = 0;
     for (int r = threadIdx.x; r < J.nred; r += TPB) {
@@ -257,12 +257,13 @@ __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
 // ---------------------------------------------------------------------------
 // a2: per-tile aggregates.  Item i is light iff n q_i <= Q, i.e. q_i <= Qn.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void load_tile_items(const float* w, int64_t base, int cnt, float v[IPT]) {
+__device__ __forceinline__ void load_tile_items(const float* wp, int64_t base, int cnt, float v[IPT]) {
+    const WRS_GLOBAL float* w = glb(wp);
     const int i0 = threadIdx.x * IPT;
     if ((IPT % 4) == 0 && i0 + IPT <= cnt && ((((uintptr_t)(w + base + i0)) & 15) == 0)) {
 #pragma unroll
         for (int r = 0; r < IPT / 4; ++r) {
-            const float4 x = *(const float4*)(w + base + i0 + 4 * r);
+            const vfloat4 x = *(const WRS_GLOBAL vfloat4*)(w + base + i0 + 4 * r);
             v[4 * r] = x.x;
             v[4 * r + 1] = x.y;
             v[4 * r + 2] = x.z;
@@ -291,26 +292,26 @@ constexpr int AGG_VEC = TILE / 256;  // float4 loads per lane
 __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
     __shared__ int s_job;
     int64_t lb;
-    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
     const BuildScalars* sc = J.sc;
     if (sc->status != WRS_OK) return;
     const int64_t c = lb * TILES_PER_AGG_BLOCK + (threadIdx.x >> 6);
     if (c >= J.ntiles) return;
     const int lane = threadIdx.x & 63;
-    const int G = sc->G;
-    const uint32_t wthr = sc->wthr;
-    const u128 Q = sc->Q;
+    const int G = uni(sc->G);
+    const uint32_t wthr = uni(sc->wthr);
+    const u128 Q = uni(sc->Q);
     const int64_t n = J.n;
     const int64_t base = c * TILE;
     const int cnt = (int)min((int64_t)TILE, n - base);
-    const float* w = J.w + base;
+    const WRS_GLOBAL float* w = glb(J.w) + base;
     const bool vec = (cnt == TILE) && ((((uintptr_t)w) & 15) == 0);
     float v[4 * AGG_VEC];
 #pragma unroll
     for (int r = 0; r < AGG_VEC; ++r) {
         const int i0 = r * 256 + lane * 4;
         if (vec) {
-            const float4 x = *(const float4*)(w + i0);
+            const vfloat4 x = *(const WRS_GLOBAL vfloat4*)(w + i0);
             v[4 * r] = x.x; v[4 * r + 1] = x.y; v[4 * r + 2] = x.z; v[4 * r + 3] = x.w;
         } else {
 #pragma unroll
@@ -347,10 +348,10 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
     sqh = wave_sum_u128(sqh);
     if (lane == 0) {
         const uint32_t nh = (uint32_t)cnt - nl;
-        J.NL[c] = nl;
-        J.DP[c] = (u128)nl * Q - (u128)n * sql;
-        J.EP[c] = (u128)n * sqh - (u128)nh * Q;
-        J.FH[c] = fh;
+        glb(J.NL)[c] = nl;
+        glb(J.DP)[c] = (u128)nl * Q - (u128)n * sql;
+        glb(J.EP)[c] = (u128)n * sqh - (u128)nh * Q;
+        glb(J.FH)[c] = fh;
     }
 }
 
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
     __shared__ ScanTmp tmp;
     __shared__ int s_w[TPB / 64];
     int64_t lb;
-    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
     if (J.sc->status != WRS_OK) return;
     const int64_t C = J.ntiles;
     const int64_t t0 = lb * SCAN_SEG + (int64_t)threadIdx.x * SEG_PER_THREAD;
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(TPB) void k_scan_top(JobTable jt) {
     __shared__ ScanTmp tmp;
     __shared__ int s_w[TPB / 64];
     int64_t lb;
-    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
     if (J.sc->status != WRS_OK) return;
     const int S = J.nseg;
     const int per = (S + TPB - 1) / TPB;   // segments per thread (<= 4 for n < 2^31)
@@ -495,7 +496,7 @@ __global__ __launch_bounds__(TPB) void k_scan_top(JobTable jt) {
     }
     if (threadIdx.x == 0) {
         const int64_t C = J.ntiles;
-        const int ks = J.sc->kshift;
+        const int ks = uni(J.sc->kshift);
         J.NL[C] = nl_tot;
         J.DP[C] = dp_tot;
         J.EP[C] = ep_tot;
@@ -509,13 +510,13 @@ __global__ __launch_bounds__(TPB) void k_scan_top(JobTable jt) {
 __global__ __launch_bounds__(TPB) void k_scan_fix(JobTable jt) {
     __shared__ int s_job;
     int64_t lb;
-    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
     if (J.sc->status != WRS_OK) return;
     const int64_t C = J.ntiles;
     const uint32_t pnl = J.sNL[lb];
     const u128 pdp = J.sDP[lb], pep = J.sEP[lb];
     const int nxt = J.sFH[lb + 1];
-    const int ks = J.sc->kshift;
+    const int ks = uni(J.sc->kshift);
     for (int e = 0; e < SEG_PER_THREAD; ++e) {
         const int64_t c = lb * SCAN_SEG + (int64_t)e * TPB + threadIdx.x;
         if (c < C) {
@@ -558,14 +559,14 @@ __global__ __launch_bounds__(TPB) void k_scan_fix(JobTable jt) {
 __global__ __launch_bounds__(TPB) void k_split(JobTable jt) {
     __shared__ int s_job;
     int64_t lb;
-    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
     if (J.sc->status != WRS_OK) return;
     const int64_t b = lb * TPB + threadIdx.x;
     if (b >= J.npack) return;
     const int64_t C = J.ntiles;
     const int64_t s0 = b * PACK_STEPS;
-    const uint64_t* DP = J.DP64;
-    const uint64_t* EP = J.EP64;
+    const WRS_GLOBAL uint64_t* DP = glb(J.DP64);
+    const WRS_GLOBAL uint64_t* EP = glb(J.EP64);
     // largest x with: x == 0, or light event x precedes heavy event s0-x+1
     int64_t lo = max((int64_t)0, s0 - C), hi = min(s0, C);
     while (lo < hi) {
@@ -574,7 +575,7 @@ __global__ __launch_bounds__(TPB) void k_split(JobTable jt) {
         const bool ok = (y1 > C) || (x < C && DP[x] < EP[y1]);
         if (ok) lo = x; else hi = x - 1;
     }
-    J.pstart[b] = (int32_t)lo;
+    glb(J.pstart)[b] = (int32_t)lo;
 }
 
 // A tile staged for the merge.  Lights sit at [0, nl) in index order with the
@@ -603,14 +604,23 @@ struct PackShared {
     int s_job;
 };
 
-__device__ __forceinline__ void fetch_tile(const JobDesc& J, int64_t c, float v[IPT]) {
+// A tile's weights and its exact prefix keys, loaded ahead of the fill.
+struct TileFetch {
+    float v[IPT];
+    uint64_t dp, ep;  // DP64[c], EP64[c]
+};
+
+__device__ __forceinline__ void fetch_tile(const JobDesc& J, int64_t c, TileFetch& f) {
     if (c >= J.ntiles) {
 #pragma unroll
-        for (int e = 0; e < IPT; ++e) v[e] = 0.0f;
+        for (int e = 0; e < IPT; ++e) f.v[e] = 0.0f;
+        f.dp = f.ep = 0;
         return;
     }
     const int64_t base = c * TILE;
-    load_tile_items(J.w, base, (int)min((int64_t)TILE, J.n - base), v);
+    f.dp = glb(J.DP64)[c];
+    f.ep = glb(J.EP64)[c];
+    load_tile_items(J.w, base, (int)min((int64_t)TILE, J.n - base), f.v);
 }
 
 // n q(w) / 2^kshift rounded to nearest (ties up): the item's size in key
@@ -678,8 +688,9 @@ __device__ __forceinline__ void block_scan64(uint32_t cnt, uint64_t a, uint64_t 
 // Fill slot S with tile c from the prefetched weights v (c == C: empty tile).
 // Keys: the exact tile prefix (DP64, EP64) plus the rounded sizes of the items
 // before (lights) or through (heavies) each item in the tile.
-__device__ void fill_tile(PackSlot& S, int64_t c, const float v[IPT], const JobDesc& J, const BuildScalars& sc,
+__device__ void fill_tile(PackSlot& S, int64_t c, const TileFetch& f, const JobDesc& J, const BuildScalars& sc,
                           ScanTmp64& tmp) {
+    const float* v = f.v;
     __syncthreads();  // every thread is done with the slot's previous contents
     if (c >= J.ntiles) {
         if (threadIdx.x == 0) {
@@ -714,8 +725,8 @@ __device__ void fill_tile(PackSlot& S, int64_t c, const float v[IPT], const JobD
     block_scan64(nl, dsum, esum, nl_ex, d_ex, e_ex, nl_tot, tmp);
     uint32_t lr = nl_ex;
     uint32_t hr = (uint32_t)i0 - nl_ex;  // heavies before this thread's items
-    uint64_t dacc = J.DP64[c] + d_ex;
-    uint64_t eacc = J.EP64[c] + e_ex;
+    uint64_t dacc = f.dp + d_ex;
+    uint64_t eacc = f.ep + e_ex;
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         if (i0 + e < cnt) {
@@ -777,8 +788,10 @@ __device__ __forceinline__ int heavies_upto(const PackSlot& S, int from, uint64_
 }
 
 __device__ __forceinline__ void store_entry(wrs_entry* table, int64_t item, float t, int32_t alias) {
-    uint2 v = make_uint2(__float_as_uint(t), (uint32_t)alias);
-    *(uint2*)(table + item) = v;
+    vuint2 v;
+    v.x = __float_as_uint(t);
+    v.y = (uint32_t)alias;
+    *(WRS_GLOBAL vuint2*)(table + item) = v;
 }
 
 __device__ __forceinline__ float light_t(float w, const BuildScalars& sc) {
@@ -788,22 +801,22 @@ __device__ __forceinline__ float light_t(float w, const BuildScalars& sc) {
 __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
     __shared__ PackShared sh;
     int64_t lb;
-    const JobDesc& J = job_of_block(jt, lb, &sh.s_job);
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &sh.s_job, xcd_contiguous_block()));
     if (J.sc->status != WRS_OK) return;
-    const BuildScalars sc = *J.sc;
+    const BuildScalars sc = scalars_uniform(J.sc);
     const int64_t C = J.ntiles;
     const int64_t s0 = lb * PACK_STEPS;
     const int64_t s1 = min(s0 + (int64_t)PACK_STEPS, 2 * C);
-    const int64_t x0 = J.pstart[lb];
+    const int64_t x0 = glb(J.pstart)[lb];
     const int64_t y0 = s0 - x0;
-    float va[IPT], vb[IPT];
+    TileFetch va, vb;
     fetch_tile(J, x0, va);
     if (y0 != x0) fetch_tile(J, y0, vb);
     for (int i = threadIdx.x; i < PACK_STEPS + 2; i += TPB) {
         const int64_t xi = x0 + i, yi = y0 + i;
-        sh.dp[i] = (xi <= C) ? J.DP64[xi] : ~0ull;
-        sh.ep[i] = (yi <= C) ? J.EP64[yi] : ~0ull;
-        sh.fh[i] = (yi <= C) ? J.FH[yi] : FH_NONE;
+        sh.dp[i] = (xi <= C) ? glb(J.DP64)[xi] : ~0ull;
+        sh.ep[i] = (yi <= C) ? glb(J.EP64)[yi] : ~0ull;
+        sh.fh[i] = (yi <= C) ? glb(J.FH)[yi] : FH_NONE;
     }
     int sa = 0, sb = 0;
     fill_tile(sh.slot[0], x0, va, J, sc, sh.tmp);  // its first barrier also publishes the window
@@ -836,7 +849,7 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
         const int64_t nt = heavy_ev ? y + 1 : x + 1;
         const bool reuse = heavy_ev ? (nt == x) : (nt == y);
         const bool need = (s + 1 < s1) && !reuse;
-        float vn[IPT];
+        TileFetch vn;
         if (need) fetch_tile(J, nt, vn);
         const int nlx = A.nl, nhy = B.nh, offB = B.nl;
         const int64_t abase = A.tile * TILE, bbase = B.tile * TILE;
@@ -953,12 +966,12 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
 __global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
     __shared__ int s_job;
     int64_t lb;
-    const JobDesc& J = job_of_block(jt, lb, &s_job);
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
     if (J.sc != nullptr && J.sc->status != WRS_OK) return;
     const int64_t k = J.k;
     const uint64_t n = (uint64_t)J.n;
     const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
-    const uint64_t* table = (const uint64_t*)J.table;
+    const WRS_GLOBAL uint64_t* table = (const WRS_GLOBAL uint64_t*)glb(J.table);
     const int64_t s0 = lb * SAMPLES_PER_BLOCK + threadIdx.x;
     uint32_t r[SAMPLE_UNROLL];
     float u[SAMPLE_UNROLL];
@@ -985,7 +998,7 @@ __global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
         if (s < k) {
             const float t = __uint_as_float((uint32_t)ent[e]);
             const int32_t a = (int32_t)(uint32_t)(ent[e] >> 32);
-            J.out[s] = (u[e] < t) ? (int32_t)r[e] : a;
+            glb(J.out)[s] = (u[e] < t) ? (int32_t)r[e] : a;
         }
     }
 }

@@ -148,14 +148,108 @@ __device__ __forceinline__ void block_scan3(uint32_t cnt, u128 a, u128 b, uint32
     __syncthreads();
 }
 
-// Locate the job and the block index within the job for the current block.
-__device__ __forceinline__ const JobDesc& job_of_block(const JobTable& jt, int64_t& lb, int* s_job) {
+// Global-memory view of a pointer.  Pointers read from a job descriptor are
+// generic to the compiler, and generic (flat) accesses count against the LDS
+// wait counter too, so every LDS wait after one would also wait for it; the
+// hot kernels access device memory through this view instead.
+#define WRS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ WRS_GLOBAL T* glb(T* p) {
+    return (WRS_GLOBAL T*)p;
+}
+// Plain clang vectors: HIP's float4 / uint2 classes cannot be read or written
+// through an address-space-qualified pointer.
+typedef float vfloat4 __attribute__((ext_vector_type(4)));
+typedef uint32_t vuint2 __attribute__((ext_vector_type(2)));
+
+// Values that every lane holds alike, moved to scalar registers.  The job
+// descriptor and the build scalars are read once per block this way; left in
+// vector registers they are reloaded per lane inside loops, and each reload's
+// wait also waits for every load in flight (the tile prefetches included).
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int32_t uni(int32_t v) { return (int32_t)uni((uint32_t)v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v) {
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+__device__ __forceinline__ int64_t uni(int64_t v) { return (int64_t)uni((uint64_t)v); }
+__device__ __forceinline__ double uni(double v) {
+    return __longlong_as_double((long long)uni((uint64_t)__double_as_longlong(v)));
+}
+__device__ __forceinline__ u128 uni(u128 v) { return ((u128)uni((uint64_t)(v >> 64)) << 64) | uni((uint64_t)v); }
+template <class T>
+__device__ __forceinline__ T* uni(T* p) {
+    return (T*)uni((uint64_t)(uintptr_t)p);
+}
+
+__device__ __forceinline__ JobDesc job_uniform(const JobDesc& J) {
+    JobDesc u;
+    u.w = uni(J.w);
+    u.table = uni(J.table);
+    u.out = uni(J.out);
+    u.n = uni(J.n);
+    u.k = uni(J.k);
+    u.seed = uni(J.seed);
+    u.first_counter = uni(J.first_counter);
+    u.stream_id = uni(J.stream_id);
+    u.ntiles = uni(J.ntiles);
+    u.nred = uni(J.nred);
+    u.nseg = uni(J.nseg);
+    u.sc = uni(J.sc);
+    u.red = uni(J.red);
+    u.redinfo = uni(J.redinfo);
+    u.NL = uni(J.NL);
+    u.DP = uni(J.DP);
+    u.EP = uni(J.EP);
+    u.DP64 = uni(J.DP64);
+    u.EP64 = uni(J.EP64);
+    u.FH = uni(J.FH);
+    u.pstart = uni(J.pstart);
+    u.npack = uni(J.npack);
+    u.sNL = uni(J.sNL);
+    u.sDP = uni(J.sDP);
+    u.sEP = uni(J.sEP);
+    u.sFH = uni(J.sFH);
+    return u;
+}
+
+__device__ __forceinline__ BuildScalars scalars_uniform(const BuildScalars* p) {
+    BuildScalars u;
+    u.status = uni(p->status);
+    u.G = uni(p->G);
+    u.pad[0] = u.pad[1] = 0;
+    u.Q = uni(p->Q);
+    u.W_hi = uni(p->W_hi);
+    u.W_lo = uni(p->W_lo);
+    u.Qd = uni(p->Qd);
+    u.rQ = uni(p->rQ);
+    u.nscale = uni(p->nscale);
+    u.Qn = uni(p->Qn);
+    u.npos = uni(p->npos);
+    u.kshift = uni(p->kshift);
+    u.wthr = uni(p->wthr);
+    u.tscale = uni(p->tscale);
+    u.Qk = uni(p->Qk);
+    u.pad3 = 0;
+    return u;
+}
+
+// Workgroups are dispatched to the 8 XCDs round robin (block b to XCD b mod 8),
+// each XCD with its own L2.  This bijection gives each XCD a contiguous run of
+// block indices, in dispatch order, so neighbouring work shares an L2.
+__device__ __forceinline__ int64_t xcd_contiguous_block() {
+    const int64_t b = blockIdx.x, g = gridDim.x;
+    const int64_t q = g >> 3, r = g & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+// Locate the job and the block index within the job for block b of the grid.
+__device__ __forceinline__ const JobDesc& job_of_block(const JobTable& jt, int64_t& lb, int* s_job,
+                                                       int64_t b = blockIdx.x) {
     if (jt.jobs == nullptr) {
-        lb = blockIdx.x;
+        lb = b;
         return jt.one;
     }
     const int64_t* off = jt.off + (int64_t)jt.phase * (jt.njobs + 1);
-    const int64_t b = blockIdx.x;
     if (threadIdx.x == 0) {
         int lo = 0, hi = jt.njobs - 1;
         while (lo < hi) {
