@@ -649,19 +649,9 @@ __device__ __forceinline__ void block_scan64(uint32_t cnt, uint64_t a, uint64_t 
                                              uint64_t& b_ex, uint32_t& cnt_tot, ScanTmp64& tmp) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    uint32_t ci = cnt;
-    uint64_t ai = a, bi = b;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t cu = __shfl_up(ci, d, 64);
-        const uint64_t au = __shfl_up((unsigned long long)ai, d, 64);
-        const uint64_t bu = __shfl_up((unsigned long long)bi, d, 64);
-        if (lane >= d) {
-            ci += cu;
-            ai += au;
-            bi += bu;
-        }
-    }
+    const uint32_t ci = wave_incl_scan(cnt);
+    const uint64_t ai = wave_incl_scan(a);
+    const uint64_t bi = wave_incl_scan(b);
     if (lane == 63) {
         tmp.c[wv] = ci;
         tmp.a[wv] = ai;

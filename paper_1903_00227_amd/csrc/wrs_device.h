@@ -94,6 +94,44 @@ __device__ __forceinline__ void dd_add(double& ah, double& al, double bh, double
 }
 
 // ---------------------------------------------------------------------------
+// Wave-wide (64 lanes) inclusive prefix sums in registers: DPP row shifts by
+// 1, 2, 4, 8 inside each row of 16 lanes, then the row broadcasts of lanes 15
+// and 31 carry the row totals forward.  A lane whose source lies outside its
+// row, or whose row is masked off, adds 0.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    const uint32_t lo = dpp_u32<CTRL, ROW_MASK>((uint32_t)v);
+    const uint32_t hi = dpp_u32<CTRL, ROW_MASK>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+constexpr int DPP_ROW_SHR = 0x110, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += dpp_u32<DPP_ROW_SHR + 1, 0xf>(x);
+    x += dpp_u32<DPP_ROW_SHR + 2, 0xf>(x);
+    x += dpp_u32<DPP_ROW_SHR + 4, 0xf>(x);
+    x += dpp_u32<DPP_ROW_SHR + 8, 0xf>(x);
+    x += dpp_u32<DPP_ROW_BCAST15, 0xa>(x);
+    x += dpp_u32<DPP_ROW_BCAST31, 0xc>(x);
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
+    x += dpp_u64<DPP_ROW_SHR + 1, 0xf>(x);
+    x += dpp_u64<DPP_ROW_SHR + 2, 0xf>(x);
+    x += dpp_u64<DPP_ROW_SHR + 4, 0xf>(x);
+    x += dpp_u64<DPP_ROW_SHR + 8, 0xf>(x);
+    x += dpp_u64<DPP_ROW_BCAST15, 0xa>(x);
+    x += dpp_u64<DPP_ROW_BCAST31, 0xc>(x);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
 // Block-wide (TPB = 256 threads, 4 waves of 64) exclusive scans.
 // ---------------------------------------------------------------------------
 struct ScanTmp {
