@@ -39,7 +39,7 @@ static constexpr int32_t FH_NONE = 0x7fffffff;
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BuildLayout {
-    size_t sc, red, redinfo, NL, DP, EP, DP64, EP64, FH, pstart, sNL, sDP, sEP, sFH, total;
+    size_t sc, red, redinfo, NL, DP, EP, DP64, EP64, FH, WP, PO, pstart, sNL, sDP, sEP, sFH, total;
 };
 
 static int64_t pack_blocks(int64_t C) { return cdiv(2 * C, PACK_STEPS); }
@@ -59,6 +59,8 @@ static BuildLayout layout_for(int64_t n) {
     L.DP64 = o;    o = align256(o + sizeof(uint64_t) * (C + 1));
     L.EP64 = o;    o = align256(o + sizeof(uint64_t) * (C + 1));
     L.FH = o;      o = align256(o + sizeof(int32_t) * (C + 1));
+    L.WP = o;      o = align256(o + sizeof(float) * C * TILE);
+    L.PO = o;      o = align256(o + sizeof(uint16_t) * C * TILE);
     L.pstart = o;  o = align256(o + sizeof(int32_t) * pack_blocks(C));
     L.sNL = o;     o = align256(o + sizeof(uint32_t) * (S + 1));
     L.sDP = o;     o = align256(o + sizeof(u128) * (S + 1));
@@ -86,6 +88,8 @@ void build_ws_layout(JobDesc& J, void* ws, int64_t n) {
     J.DP64 = (uint64_t*)(b + L.DP64);
     J.EP64 = (uint64_t*)(b + L.EP64);
     J.FH = (int32_t*)(b + L.FH);
+    J.WP = (float*)(b + L.WP);
+    J.PO = (uint16_t*)(b + L.PO);
     J.pstart = (int32_t*)(b + L.pstart);
     J.npack = (int32_t)pack_blocks(J.ntiles);
     J.sNL = (uint32_t*)(b + L.sNL);
@@ -257,101 +261,147 @@ __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
 // ---------------------------------------------------------------------------
 // a2: per-tile aggregates.  Item i is light iff n q_i <= Q, i.e. q_i <= Qn.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void load_tile_items(const float* wp, int64_t base, int cnt, float v[IPT]) {
-    const WRS_GLOBAL float* w = glb(wp);
-    const int i0 = threadIdx.x * IPT;
-    if ((IPT % 4) == 0 && i0 + IPT <= cnt && ((((uintptr_t)(w + base + i0)) & 15) == 0)) {
-#pragma unroll
-        for (int r = 0; r < IPT / 4; ++r) {
-            const vfloat4 x = *(const WRS_GLOBAL vfloat4*)(w + base + i0 + 4 * r);
-            v[4 * r] = x.x;
-            v[4 * r + 1] = x.y;
-            v[4 * r + 2] = x.z;
-            v[4 * r + 3] = x.w;
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < IPT; ++e) v[e] = (i0 + e < cnt) ? w[base + i0 + e] : 0.0f;
-    }
-}
-
-__device__ __forceinline__ u128 wave_sum_u128(u128 v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint64_t lo = __shfl_xor((unsigned long long)(uint64_t)v, off, 64);
-        const uint64_t hi = __shfl_xor((unsigned long long)(uint64_t)(v >> 64), off, 64);
-        v += ((u128)hi << 64) | lo;
-    }
-    return v;
-}
-
 // One wave per tile: each lane reads 4 float4 (lane-interleaved, 1 KiB per
-// instruction across the wave), so no block synchronisation is needed.
+// instruction across the wave), so the aggregates need no block
+// synchronisation.  The wave also writes the tile in partitioned order (its
+// lights, then its heavies, each in index order) with every item's offset, so
+// that the merge stages one side of a tile without classifying it again.
 constexpr int AGG_VEC = TILE / 256;  // float4 loads per lane
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
 
 __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
     __shared__ int s_job;
+    __shared__ float s_w[TILES_PER_AGG_BLOCK][TILE];
+    __shared__ uint16_t s_o[TILES_PER_AGG_BLOCK][TILE];
     int64_t lb;
     const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
     const BuildScalars* sc = J.sc;
-    if (sc->status != WRS_OK) return;
-    const int64_t c = lb * TILES_PER_AGG_BLOCK + (threadIdx.x >> 6);
-    if (c >= J.ntiles) return;
+    if (sc->status != WRS_OK) return;  // the same for the whole block
+    const int wv = threadIdx.x >> 6;
+    const int64_t c = lb * TILES_PER_AGG_BLOCK + wv;
+    const bool active = c < J.ntiles;  // the same for the whole wave
     const int lane = threadIdx.x & 63;
     const int G = uni(sc->G);
     const uint32_t wthr = uni(sc->wthr);
     const u128 Q = uni(sc->Q);
     const int64_t n = J.n;
     const int64_t base = c * TILE;
-    const int cnt = (int)min((int64_t)TILE, n - base);
-    const WRS_GLOBAL float* w = glb(J.w) + base;
-    const bool vec = (cnt == TILE) && ((((uintptr_t)w) & 15) == 0);
-    float v[4 * AGG_VEC];
+    if (active) {
+        const int cnt = (int)min((int64_t)TILE, n - base);
+        const WRS_GLOBAL float* w = glb(J.w) + base;
+        const bool vec = (cnt == TILE) && ((((uintptr_t)w) & 15) == 0);
+        float v[4 * AGG_VEC];
+        if (vec) {  // all loads in flight together
+            vfloat4 x[AGG_VEC];
 #pragma unroll
-    for (int r = 0; r < AGG_VEC; ++r) {
-        const int i0 = r * 256 + lane * 4;
-        if (vec) {
-            const vfloat4 x = *(const WRS_GLOBAL vfloat4*)(w + i0);
-            v[4 * r] = x.x; v[4 * r + 1] = x.y; v[4 * r + 2] = x.z; v[4 * r + 3] = x.w;
+            for (int r = 0; r < AGG_VEC; ++r) x[r] = *(const WRS_GLOBAL vfloat4*)(w + r * 256 + lane * 4);
+#pragma unroll
+            for (int r = 0; r < AGG_VEC; ++r) {
+                v[4 * r] = x[r].x; v[4 * r + 1] = x[r].y; v[4 * r + 2] = x[r].z; v[4 * r + 3] = x[r].w;
+            }
         } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[4 * r + e] = (i0 + e < cnt) ? w[i0 + e] : 0.0f;
-        }
-    }
-    uint32_t nl = 0;
-    u128 sql = 0, sqh = 0;
-    int fh = FH_NONE;
+            for (int r = 0; r < AGG_VEC; ++r) {
 #pragma unroll
-    for (int r = 0; r < AGG_VEC; ++r) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int i = r * 256 + lane * 4 + e;
-            if (i < cnt) {
-                const float x = v[4 * r + e];
-                const u128 q = quantize(x, G);
-                if (__float_as_uint(x) < wthr) {
-                    ++nl;
-                    sql += q;
-                } else {
-                    sqh += q;
-                    fh = min(fh, (int)(base + i));
+                for (int e = 0; e < 4; ++e) {
+                    const int i = r * 256 + lane * 4 + e;
+                    v[4 * r + e] = (i < cnt) ? w[i] : 0.0f;
                 }
             }
         }
-    }
+        // light flags, as one ballot per (load, element)
+        // (items past the tile's end hold 0, which adds nothing)
+        auto is_light = [&](int r, int e) -> bool {
+            return (r * 256 + lane * 4 + e < cnt) && (__float_as_uint(v[4 * r + e]) < wthr);
+        };
+        uint32_t nl = 0;
+        u128 sq = 0, sql = 0;
+        int fh = FH_NONE;
+        int smin = 0;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        nl += __shfl_xor(nl, off, 64);
-        fh = min(fh, __shfl_xor(fh, off, 64));
+        for (int k = 0; k < 4 * AGG_VEC; ++k) smin = min(smin, grid_shift(v[k], G));
+        if (__ballot(smin < 0) == 0) {
+            // every weight of the tile lies on the grid
+#pragma unroll
+            for (int r = 0; r < AGG_VEC; ++r) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const bool light = is_light(r, e);
+                    const u128 q = quantize_on_grid(v[4 * r + e], G);
+                    sq += q;
+                    sql += light ? q : (u128)0;
+                }
+            }
+        } else {
+            for (int k = 0; k < 4 * AGG_VEC; ++k) {
+                const bool light = is_light(k >> 2, k & 3);
+                const u128 q = quantize(v[k], G);
+                sq += q;
+                sql += light ? q : (u128)0;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < AGG_VEC; ++r) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = r * 256 + lane * 4 + e;
+                const bool light = is_light(r, e);
+                nl += (uint32_t)__popcll(__ballot(light));
+                fh = (i < cnt && !light) ? min(fh, (int)(base + i)) : fh;
+            }
+        }
+        // partitioned order: lights before item i, then the heavies after all lights
+        uint32_t lbefore = 0;  // lights in earlier loads
+#pragma unroll
+        for (int r = 0; r < AGG_VEC; ++r) {
+            uint64_t lm[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) lm[e] = __ballot(is_light(r, e));
+            uint32_t lr = lbefore + lanes_below(lm[0]) + lanes_below(lm[1]) + lanes_below(lm[2]) + lanes_below(lm[3]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = r * 256 + lane * 4 + e;
+                const bool light = (lm[e] >> lane) & 1ull;
+                const int p = light ? (int)lr : (int)(nl + (uint32_t)i - lr);
+                if (i < cnt) {
+                    s_w[wv][p] = v[4 * r + e];
+                    s_o[wv][p] = (uint16_t)i;
+                }
+                lr += light;
+            }
+            lbefore += (uint32_t)(__popcll(lm[0]) + __popcll(lm[1]) + __popcll(lm[2]) + __popcll(lm[3]));
+        }
+        fh = (int)lane63((uint32_t)wave_incl_min(fh));
+        sql = lane63(wave_incl_scan(sql));
+        const u128 sqh = lane63(wave_incl_scan(sq)) - sql;
+        if (lane == 0) {
+            const uint32_t nh = (uint32_t)cnt - nl;
+            glb(J.NL)[c] = nl;
+            glb(J.DP)[c] = (u128)nl * Q - (u128)n * sql;
+            glb(J.EP)[c] = (u128)n * sqh - (u128)nh * Q;
+            glb(J.FH)[c] = fh;
+        }
     }
-    sql = wave_sum_u128(sql);
-    sqh = wave_sum_u128(sqh);
-    if (lane == 0) {
-        const uint32_t nh = (uint32_t)cnt - nl;
-        glb(J.NL)[c] = nl;
-        glb(J.DP)[c] = (u128)nl * Q - (u128)n * sql;
-        glb(J.EP)[c] = (u128)n * sqh - (u128)nh * Q;
-        glb(J.FH)[c] = fh;
+    __syncthreads();
+    if (active) {
+        // whole tile (the arrays are padded to whole tiles); entries past the
+        // tile's item count are never read
+        WRS_GLOBAL float* wp = glb(J.WP) + base;
+        WRS_GLOBAL uint16_t* po = glb(J.PO) + base;
+#pragma unroll
+        for (int r = 0; r < AGG_VEC; ++r) {
+            const int i0 = r * 256 + lane * 4;
+            vfloat4 x;
+            x.x = s_w[wv][i0]; x.y = s_w[wv][i0 + 1]; x.z = s_w[wv][i0 + 2]; x.w = s_w[wv][i0 + 3];
+            *(WRS_GLOBAL vfloat4*)(wp + i0) = x;
+            vuint2 o;
+            o.x = (uint32_t)s_o[wv][i0] | ((uint32_t)s_o[wv][i0 + 1] << 16);
+            o.y = (uint32_t)s_o[wv][i0 + 2] | ((uint32_t)s_o[wv][i0 + 3] << 16);
+            *(WRS_GLOBAL vuint2*)(po + i0) = o;
+        }
     }
 }
 
@@ -578,167 +628,127 @@ __global__ __launch_bounds__(TPB) void k_split(JobTable jt) {
     glb(J.pstart)[b] = (int32_t)lo;
 }
 
-// A tile staged for the merge.  Lights sit at [0, nl) in index order with the
-// deficit sum before them as key; heavies at [nl, nl + nh) with the excess sum
-// through them.
-struct PackSlot {
+// The two sides of the merge staged in LDS: the lights of tile x with the
+// deficit sum before each as key, and the heavies of tile y with the excess
+// sum through each.  Both come in index order from the partitioned copy of
+// the tile that k_tileagg wrote.
+struct LightSlot {
     uint64_t key[TILE];
-    float w[TILE];        // weight of a light (its bucket keeps n w / W)
+    float w[TILE];        // a light's bucket keeps n w / W
     uint16_t off[TILE];   // item offset inside the tile
-    int32_t nl, nh;
-    int64_t tile;
 };
 
-struct ScanTmp64 {
-    uint64_t a[TPB / 64];
-    uint64_t b[TPB / 64];
-    uint32_t c[TPB / 64];
+struct HeavySlot {
+    uint64_t key[TILE];
+    uint16_t off[TILE];
 };
 
 struct PackShared {
-    PackSlot slot[2];
-    ScanTmp64 tmp;
-    uint64_t dp[PACK_STEPS + 2];  // DP64[x0 + i]
-    uint64_t ep[PACK_STEPS + 2];  // EP64[y0 + i]
-    int32_t fh[PACK_STEPS + 2];   // FH[y0 + i]
+    LightSlot A;
+    HeavySlot B;
+    uint64_t tmp[TPB / 64];
+    uint64_t dp[PACK_STEPS + 2];   // DP64[x0 + i]
+    uint64_t ep[PACK_STEPS + 2];   // EP64[y0 + i]
+    int32_t fh[PACK_STEPS + 2];    // FH[y0 + i]
+    uint32_t nlx[PACK_STEPS + 2];  // NL[x0 + i]
+    uint32_t nly[PACK_STEPS + 2];  // NL[y0 + i]
     int s_job;
 };
 
-// A tile's weights and its exact prefix keys, loaded ahead of the fill.
-struct TileFetch {
+// One side of a tile, loaded ahead of its fill: thread t holds the side's
+// items [t k, t k + k), k = ceil(count / TPB).
+struct SideFetch {
     float v[IPT];
-    uint64_t dp, ep;  // DP64[c], EP64[c]
+    uint32_t o[IPT];
+    uint64_t base;  // DP64[c] for the lights, EP64[c] for the heavies
+    int cnt;        // items on this side
 };
 
-__device__ __forceinline__ void fetch_tile(const JobDesc& J, int64_t c, TileFetch& f) {
-    if (c >= J.ntiles) {
+// side items [first, first + cnt) of the partitioned tile c
+__device__ __forceinline__ void fetch_side(const JobDesc& J, int64_t c, int first, int cnt, bool light,
+                                           SideFetch& f) {
+    f.cnt = cnt;
+    f.base = 0;
+    if (cnt == 0) return;
+    f.base = light ? glb(J.DP64)[c] : glb(J.EP64)[c];
+    const int k = (cnt + TPB - 1) / TPB;
+    const int j0 = (int)threadIdx.x * k;
+    const WRS_GLOBAL float* wp = glb(J.WP) + c * TILE + first;
+    const WRS_GLOBAL uint16_t* po = glb(J.PO) + c * TILE + first;
 #pragma unroll
-        for (int e = 0; e < IPT; ++e) f.v[e] = 0.0f;
-        f.dp = f.ep = 0;
-        return;
+    for (int e = 0; e < IPT; ++e) {
+        if (e < k) {
+            const int j = j0 + e;
+            if (j < cnt) {
+                f.v[e] = wp[j];
+                f.o[e] = po[j];
+            }
+        }
     }
-    const int64_t base = c * TILE;
-    f.dp = glb(J.DP64)[c];
-    f.ep = glb(J.EP64)[c];
-    load_tile_items(J.w, base, (int)min((int64_t)TILE, J.n - base), f.v);
 }
 
 // n q(w) / 2^kshift rounded to nearest (ties up): the item's size in key
-// units.  n q = (n m) 2^s on the grid; the result is below 2^62 for every
-// weight <= W.
+// units.  On the grid (s >= 0) n q = (n m) 2^s exactly; below it q is rounded
+// first.  The result is below 2^62 for every weight <= W.
 __device__ __forceinline__ uint64_t size_keyunits(float w, const BuildScalars& sc, uint32_t n) {
     const uint32_t bits = __float_as_uint(w);
     const uint32_t e = bits >> 23;
     const uint32_t m = (bits & 0x7FFFFFu) | (e ? 0x800000u : 0u);
-    const int s = (int)(e ? e : 1u) - 150 - sc.G;
-    uint64_t x;
-    int r;  // right shift
-    if (s >= 0) {
-        x = (uint64_t)m * n;
-        r = sc.kshift - s;
-    } else {
+    const int s = (int)max(e, 1u) - 150 - sc.G;
+    uint64_t x = (uint64_t)m * n;  // < 2^55
+    int r = sc.kshift - s;         // right shift
+    if (s < 0) {
         x = (uint64_t)quantize(w, sc.G) * n;
         r = sc.kshift;
     }
-    if (r <= 0) return x << min(-r, 63);
-    if (r >= 64) return 0;
-    return (x >> r) + ((x >> (r - 1)) & 1ull);
+    const uint64_t down = (x + (1ull << ((r - 1) & 63))) >> (r & 63);  // r in [1, 63]: no overflow
+    const uint64_t up = x << (r <= 0 ? min(-r, 63) : 0);
+    return r <= 0 ? up : (r >= 64 ? 0ull : down);
 }
 
-__device__ __forceinline__ void block_scan64(uint32_t cnt, uint64_t a, uint64_t b, uint32_t& cnt_ex, uint64_t& a_ex,
-                                             uint64_t& b_ex, uint32_t& cnt_tot, ScanTmp64& tmp) {
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const uint32_t ci = wave_incl_scan(cnt);
-    const uint64_t ai = wave_incl_scan(a);
-    const uint64_t bi = wave_incl_scan(b);
-    if (lane == 63) {
-        tmp.c[wv] = ci;
-        tmp.a[wv] = ai;
-        tmp.b[wv] = bi;
-    }
-    __syncthreads();
-    uint32_t cp = 0;
-    uint64_t ap = 0, bp = 0;
-    cnt_tot = 0;
-#pragma unroll
-    for (int k = 0; k < TPB / 64; ++k) {
-        if (k < wv) {
-            cp += tmp.c[k];
-            ap += tmp.a[k];
-            bp += tmp.b[k];
-        }
-        cnt_tot += tmp.c[k];
-    }
-    cnt_ex = cp + ci - cnt;
-    a_ex = ap + ai - a;
-    b_ex = bp + bi - b;
-}
-
-// Fill slot S with tile c from the prefetched weights v (c == C: empty tile).
-// Keys: the exact tile prefix (DP64, EP64) plus the rounded sizes of the items
-// before (lights) or through (heavies) each item in the tile.
-__device__ void fill_tile(PackSlot& S, int64_t c, const TileFetch& f, const JobDesc& J, const BuildScalars& sc,
-                          ScanTmp64& tmp) {
-    const float* v = f.v;
-    __syncthreads();  // every thread is done with the slot's previous contents
-    if (c >= J.ntiles) {
-        if (threadIdx.x == 0) {
-            S.nl = 0;
-            S.nh = 0;
-            S.tile = c;
-        }
-        __syncthreads();
-        return;
-    }
-    const uint32_t n = (uint32_t)J.n;
-    const int64_t base = c * TILE;
-    const int cnt = (int)min((int64_t)TILE, J.n - base);
-    const int i0 = threadIdx.x * IPT;
+// Stage one side of a tile: keys are the tile's exact prefix plus the rounded
+// sizes of the side's items before (lights) or through (heavies) each item.
+template <bool LIGHT>
+__device__ __forceinline__ void fill_side(uint64_t* key, float* wl, uint16_t* off, const SideFetch& f,
+                                          const BuildScalars& sc, uint32_t n, uint64_t* tmp) {
+    const int k = (f.cnt + TPB - 1) / TPB;
+    const int j0 = (int)threadIdx.x * k;
     const uint64_t Qk = sc.Qk;
-    bool light[IPT];
     uint64_t inc[IPT];
-    uint32_t nl = 0;
-    uint64_t dsum = 0, esum = 0;
+    uint64_t sum = 0;
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
-        const bool valid = i0 + e < cnt;
-        light[e] = valid && (__float_as_uint(v[e]) < sc.wthr);
-        const uint64_t z = size_keyunits(v[e], sc, n);
-        inc[e] = !valid ? 0ull : (light[e] ? Qk - z : z - Qk);
-        nl += light[e];
-        dsum += light[e] ? inc[e] : 0ull;
-        esum += light[e] ? 0ull : inc[e];
+        inc[e] = 0;
+        if (e < k && j0 + e < f.cnt) {
+            const uint64_t z = size_keyunits(f.v[e], sc, n);
+            inc[e] = LIGHT ? Qk - z : z - Qk;
+            sum += inc[e];
+        }
     }
-    uint32_t nl_ex, nl_tot;
-    uint64_t d_ex, e_ex;
-    block_scan64(nl, dsum, esum, nl_ex, d_ex, e_ex, nl_tot, tmp);
-    uint32_t lr = nl_ex;
-    uint32_t hr = (uint32_t)i0 - nl_ex;  // heavies before this thread's items
-    uint64_t dacc = f.dp + d_ex;
-    uint64_t eacc = f.ep + e_ex;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t incl = wave_incl_scan(sum);
+    if (lane == 63) tmp[wv] = incl;
+    __syncthreads();  // also: every thread is done with the slot's previous contents
+    uint64_t acc = f.base + incl - sum;
+#pragma unroll
+    for (int w = 0; w < TPB / 64; ++w)
+        if (w < wv) acc += tmp[w];
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
-        if (i0 + e < cnt) {
-            if (light[e]) {
-                S.key[lr] = dacc;
-                S.w[lr] = v[e];
-                S.off[lr] = (uint16_t)(i0 + e);
-                dacc += inc[e];
-                ++lr;
-            } else {
-                eacc += inc[e];
-                const int p = (int)(nl_tot + hr);
-                S.key[p] = eacc;
-                S.off[p] = (uint16_t)(i0 + e);
-                ++hr;
+        if (e < k) {
+            const int j = j0 + e;
+            if (j < f.cnt) {
+                if (LIGHT) {
+                    key[j] = acc;
+                    wl[j] = f.v[e];
+                    acc += inc[e];
+                } else {
+                    acc += inc[e];
+                    key[j] = acc;
+                }
+                off[j] = (uint16_t)f.o[e];
             }
         }
-    }
-    if (threadIdx.x == 0) {
-        S.nl = (int)nl_tot;
-        S.nh = cnt - (int)nl_tot;
-        S.tile = c;
     }
     __syncthreads();
 }
@@ -767,16 +777,6 @@ __device__ __forceinline__ int wave_search(const uint64_t* key, int from, int to
     return lo;
 }
 
-// number of lights in [from, nl) with key < v, plus from
-__device__ __forceinline__ int lights_below(const PackSlot& S, int from, uint64_t v) {
-    return wave_search<false>(S.key, from, S.nl, v);
-}
-
-// number of heavies in [from, nh) with key <= v, plus from
-__device__ __forceinline__ int heavies_upto(const PackSlot& S, int from, uint64_t v) {
-    return wave_search<true>(S.key + S.nl, from, S.nh, v);
-}
-
 __device__ __forceinline__ void store_entry(wrs_entry* table, int64_t item, float t, int32_t alias) {
     vuint2 v;
     v.x = __float_as_uint(t);
@@ -794,26 +794,39 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
     const JobDesc J = job_uniform(job_of_block(jt, lb, &sh.s_job, xcd_contiguous_block()));
     if (J.sc->status != WRS_OK) return;
     const BuildScalars sc = scalars_uniform(J.sc);
+    const uint32_t n32 = (uint32_t)J.n;
     const int64_t C = J.ntiles;
     const int64_t s0 = lb * PACK_STEPS;
     const int64_t s1 = min(s0 + (int64_t)PACK_STEPS, 2 * C);
     const int64_t x0 = glb(J.pstart)[lb];
     const int64_t y0 = s0 - x0;
-    TileFetch va, vb;
-    fetch_tile(J, x0, va);
-    if (y0 != x0) fetch_tile(J, y0, vb);
     for (int i = threadIdx.x; i < PACK_STEPS + 2; i += TPB) {
         const int64_t xi = x0 + i, yi = y0 + i;
         sh.dp[i] = (xi <= C) ? glb(J.DP64)[xi] : ~0ull;
         sh.ep[i] = (yi <= C) ? glb(J.EP64)[yi] : ~0ull;
         sh.fh[i] = (yi <= C) ? glb(J.FH)[yi] : FH_NONE;
+        sh.nlx[i] = glb(J.NL)[min(xi, C)];
+        sh.nly[i] = glb(J.NL)[min(yi, C)];
     }
-    int sa = 0, sb = 0;
-    fill_tile(sh.slot[0], x0, va, J, sc, sh.tmp);  // its first barrier also publishes the window
-    if (y0 != x0) {
-        sb = 1;
-        fill_tile(sh.slot[1], y0, vb, J, sc, sh.tmp);
+    __syncthreads();
+    // lights / heavies of tile c, from the window
+    auto tile_cnt = [&](int64_t c) -> int { return (int)min((int64_t)TILE, J.n - c * TILE); };
+    auto lights_of = [&](int64_t c) -> int {
+        return c < C ? (int)(sh.nlx[c - x0 + 1] - sh.nlx[c - x0]) : 0;
+    };
+    auto heavies_of = [&](int64_t c) -> int {
+        return c < C ? tile_cnt(c) - (int)(sh.nly[c - y0 + 1] - sh.nly[c - y0]) : 0;
+    };
+    SideFetch fa, fb;
+    {
+        const int la = lights_of(x0);
+        fetch_side(J, x0, 0, la, true, fa);
+        const int hb = heavies_of(y0);
+        fetch_side(J, y0, y0 < C ? tile_cnt(y0) - hb : 0, hb, false, fb);
     }
+    fill_side<true>(sh.A.key, sh.A.w, sh.A.off, fa, sc, n32, sh.tmp);
+    fill_side<false>(sh.B.key, nullptr, sh.B.off, fb, sc, n32, sh.tmp);
+    int nlx = fa.cnt, nhy = fb.cnt;
     int64_t x = x0, y = y0;
     // DPkey(x) < v, with DPkey(C) = +infinity
     auto dpkey_lt = [&](int64_t xx, uint64_t v) -> bool { return xx < C && sh.dp[xx - x0] < v; };
@@ -821,35 +834,39 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
     if (s0 > 0) {
         const bool last_light = x >= 1 && (y == 0 || !dpkey_lt(x, sh.ep[0]));  // EP[y] <= DPkey(x)
         if (last_light) {
-            ph = (x < C) ? heavies_upto(sh.slot[sb], 0, sh.dp[0]) : 0;
+            ph = (x < C) ? wave_search<true>(sh.B.key, 0, nhy, sh.dp[0]) : 0;
         } else {
-            pl = lights_below(sh.slot[sa], 0, sh.ep[0]);
+            pl = wave_search<false>(sh.A.key, 0, nlx, sh.ep[0]);
         }
     }
     const double tscale = sc.tscale;
+    const LightSlot& A = sh.A;
+    const HeavySlot& B = sh.B;
     for (int64_t s = s0; s < s1; ++s) {
-        const PackSlot& A = sh.slot[sa];
-        const PackSlot& B = sh.slot[sb];
         const int xi = (int)(x - x0), yi = (int)(y - y0);
         const bool has_h = y + 1 <= C;
         const bool has_l = x + 1 <= C;
         const uint64_t EPn = sh.ep[yi + 1];
         const bool heavy_ev = has_h && (!has_l || !dpkey_lt(x + 1, EPn));
-        // the tile this event opens: fetched now, staged after the merge
-        const int64_t nt = heavy_ev ? y + 1 : x + 1;
-        const bool reuse = heavy_ev ? (nt == x) : (nt == y);
-        const bool need = (s + 1 < s1) && !reuse;
-        TileFetch vn;
-        if (need) fetch_tile(J, nt, vn);
-        const int nlx = A.nl, nhy = B.nh, offB = B.nl;
-        const int64_t abase = A.tile * TILE, bbase = B.tile * TILE;
+        // the tile side this event opens: fetched now, staged after the merge
+        const bool need = s + 1 < s1;
+        SideFetch fn;
+        if (need) {
+            if (heavy_ev) {
+                const int hc = heavies_of(y + 1);
+                fetch_side(J, y + 1, y + 1 < C ? tile_cnt(y + 1) - hc : 0, hc, false, fn);
+            } else {
+                fetch_side(J, x + 1, 0, lights_of(x + 1), true, fn);
+            }
+        }
+        const int64_t abase = x * TILE, bbase = y * TILE;
         int nlc, nhc;
         if (heavy_ev) {
             nhc = nhy - ph;
-            nlc = lights_below(A, pl, EPn) - pl;
+            nlc = wave_search<false>(A.key, pl, nlx, EPn) - pl;
         } else {
             nlc = nlx - pl;
-            nhc = (y < C) ? heavies_upto(B, ph, sh.dp[xi + 1]) - ph : 0;
+            nhc = (y < C) ? wave_search<true>(B.key, ph, nhy, sh.dp[xi + 1]) - ph : 0;
         }
         const int32_t nextH = has_h ? sh.fh[yi + 1] : FH_NONE;
         const uint64_t Dend = (x < C) ? sh.dp[xi + 1] : sh.dp[xi];
@@ -857,7 +874,7 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
         if (nhc == 0 && nlc > 0) {
             // lights only: all take the same alias; lanes take consecutive lights
             const bool hv = ph < nhy;
-            const int32_t al = hv ? (int32_t)(bbase + B.off[offB + ph]) : nextH;
+            const int32_t al = hv ? (int32_t)(bbase + B.off[ph]) : nextH;
             for (int d = threadIdx.x; d < nlc; d += TPB) {
                 const int lp = pl + d;
                 const int64_t own = abase + A.off[lp];
@@ -873,12 +890,12 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
             // heavies only: each keeps 1 + (E - D) with the same next light
             const uint64_t Dn = (pl < nlx) ? A.key[pl] : Dend;
             for (int d = threadIdx.x; d < nhc; d += TPB) {
-                const int hp = offB + ph + d;
+                const int hp = ph + d;
                 float t = (float)(1.0 + (double)(int64_t)(B.key[hp] - Dn) * tscale);
                 t = fminf(fmaxf(t, 0.0f), 1.0f);
                 const int64_t own = bbase + B.off[hp];
-                const int32_t al = (ph + d + 1 < nhy) ? (int32_t)(bbase + B.off[hp + 1])
-                                                      : (nextH != FH_NONE ? nextH : (int32_t)own);
+                const int32_t al = (hp + 1 < nhy) ? (int32_t)(bbase + B.off[hp + 1])
+                                                  : (nextH != FH_NONE ? nextH : (int32_t)own);
                 store_entry(J.table, own, t, al);
             }
         } else if (m > 0) {
@@ -890,21 +907,21 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                 int jlo = max(0, d0 - nlc), jhi = min(d0, nhc);
                 while (jlo < jhi) {
                     const int mid = (jlo + jhi + 1) >> 1;
-                    const bool ok = (d0 - mid >= nlc) || (B.key[offB + ph + mid - 1] <= A.key[pl + d0 - mid]);
+                    const bool ok = (d0 - mid >= nlc) || (B.key[ph + mid - 1] <= A.key[pl + d0 - mid]);
                     if (ok) jlo = mid; else jhi = mid - 1;
                 }
                 int j = jlo, i = d0 - jlo;
                 for (int d = d0; d < d1; ++d) {
-                    const bool take_h = (j < nhc) && (i >= nlc || B.key[offB + ph + j] <= A.key[pl + i]);
+                    const bool take_h = (j < nhc) && (i >= nlc || B.key[ph + j] <= A.key[pl + i]);
                     if (take_h) {
-                        const int hp = offB + ph + j;
+                        const int hp = ph + j;
                         const uint64_t E = B.key[hp];
                         const uint64_t Dn = (pl + i < nlx) ? A.key[pl + i] : Dend;
                         float t = (float)(1.0 + (double)(int64_t)(E - Dn) * tscale);
                         t = fminf(fmaxf(t, 0.0f), 1.0f);
                         const int64_t own = bbase + B.off[hp];
-                        const int32_t al = (ph + j + 1 < nhy) ? (int32_t)(bbase + B.off[hp + 1])
-                                                              : (nextH != FH_NONE ? nextH : (int32_t)own);
+                        const int32_t al = (hp + 1 < nhy) ? (int32_t)(bbase + B.off[hp + 1])
+                                                          : (nextH != FH_NONE ? nextH : (int32_t)own);
                         store_entry(J.table, own, t, al);
                         ++j;
                     } else {
@@ -913,7 +930,7 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                         float t = light_t(A.w[lp], sc);
                         int32_t al;
                         if (ph + j < nhy) {
-                            al = (int32_t)(bbase + B.off[offB + ph + j]);
+                            al = (int32_t)(bbase + B.off[ph + j]);
                         } else if (nextH != FH_NONE) {
                             al = nextH;
                         } else {
@@ -931,20 +948,16 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
         if (heavy_ev) {
             ++y;
             ph = 0;
-            if (reuse) {
-                sb = sa;
-            } else {
-                sb = 1 - sa;
-                if (need) fill_tile(sh.slot[sb], y, vn, J, sc, sh.tmp);
+            if (need) {
+                fill_side<false>(sh.B.key, nullptr, sh.B.off, fn, sc, n32, sh.tmp);
+                nhy = fn.cnt;
             }
         } else {
             ++x;
             pl = 0;
-            if (reuse) {
-                sa = sb;
-            } else {
-                sa = 1 - sb;
-                if (need) fill_tile(sh.slot[sa], x, vn, J, sc, sh.tmp);
+            if (need) {
+                fill_side<true>(sh.A.key, sh.A.w, sh.A.off, fn, sc, n32, sh.tmp);
+                nlx = fn.cnt;
             }
         }
     }

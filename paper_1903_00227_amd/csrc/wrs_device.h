@@ -42,6 +42,26 @@ __device__ __forceinline__ u128 quantize(float w, int G) {
     return (u128)(r + ((rem > half) || (rem == half && (r & 1u))));
 }
 
+// Exponent of w on the grid: w = m 2^s (s < 0: below the grid).
+__device__ __forceinline__ int grid_shift(float w, int G) {
+    const uint32_t e = __float_as_uint(w) >> 23;
+    return (int)max(e, 1u) - 150 - G;
+}
+
+// quantize() for a weight on the grid (0 <= s <= 103), without branches:
+// m 2^s with m < 2^24 is two 64-bit shifts.
+__device__ __forceinline__ u128 quantize_on_grid(float w, int G) {
+    const uint32_t bits = __float_as_uint(w);
+    const uint32_t e = bits >> 23;
+    const uint64_t m = (bits & 0x7FFFFFu) | (e ? 0x800000u : 0u);
+    const int s = min((int)max(e, 1u) - 150 - G, 103);
+    const uint64_t t = m << (s & 63);          // low word (s < 64) or high word (s >= 64)
+    const uint64_t c = m >> ((64 - s) & 63);  // bits carried into the high word, s in [1, 63]
+    const uint64_t lo = s < 64 ? t : 0ull;
+    const uint64_t hi = s < 64 ? (s == 0 ? 0ull : c) : t;
+    return ((u128)hi << 64) | lo;
+}
+
 // n * quantize(w, G), exactly: (n m) 2^s with one 32x32 product when the
 // weight lies on the grid (s >= 0), else n times the rounded q.
 __device__ __forceinline__ u128 nscaled(float w, int G, uint32_t n) {
@@ -100,8 +120,8 @@ __device__ __forceinline__ void dd_add(double& ah, double& al, double bh, double
 // row, or whose row is masked off, adds 0.
 // ---------------------------------------------------------------------------
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v, uint32_t identity = 0) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROW_MASK, 0xf, false);
 }
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
@@ -129,6 +149,44 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
     x += dpp_u64<DPP_ROW_BCAST15, 0xa>(x);
     x += dpp_u64<DPP_ROW_BCAST31, 0xc>(x);
     return x;
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ u128 dpp_u128(u128 v) {
+    const uint64_t lo = dpp_u64<CTRL, ROW_MASK>((uint64_t)v);
+    const uint64_t hi = dpp_u64<CTRL, ROW_MASK>((uint64_t)(v >> 64));
+    return ((u128)hi << 64) | lo;
+}
+
+__device__ __forceinline__ u128 wave_incl_scan(u128 x) {
+    x += dpp_u128<DPP_ROW_SHR + 1, 0xf>(x);
+    x += dpp_u128<DPP_ROW_SHR + 2, 0xf>(x);
+    x += dpp_u128<DPP_ROW_SHR + 4, 0xf>(x);
+    x += dpp_u128<DPP_ROW_SHR + 8, 0xf>(x);
+    x += dpp_u128<DPP_ROW_BCAST15, 0xa>(x);
+    x += dpp_u128<DPP_ROW_BCAST31, 0xc>(x);
+    return x;
+}
+
+// Running minimum over lanes 0..lane (signed).
+__device__ __forceinline__ int32_t wave_incl_min(int32_t x) {
+    constexpr uint32_t I = 0x7fffffffu;
+    x = min(x, (int32_t)dpp_u32<DPP_ROW_SHR + 1, 0xf>((uint32_t)x, I));
+    x = min(x, (int32_t)dpp_u32<DPP_ROW_SHR + 2, 0xf>((uint32_t)x, I));
+    x = min(x, (int32_t)dpp_u32<DPP_ROW_SHR + 4, 0xf>((uint32_t)x, I));
+    x = min(x, (int32_t)dpp_u32<DPP_ROW_SHR + 8, 0xf>((uint32_t)x, I));
+    x = min(x, (int32_t)dpp_u32<DPP_ROW_BCAST15, 0xa>((uint32_t)x, I));
+    x = min(x, (int32_t)dpp_u32<DPP_ROW_BCAST31, 0xc>((uint32_t)x, I));
+    return x;
+}
+
+// Value of lane 63 (the wave total after an inclusive scan), to every lane.
+__device__ __forceinline__ uint32_t lane63(uint32_t v) { return __builtin_amdgcn_readlane(v, 63); }
+__device__ __forceinline__ uint64_t lane63(uint64_t v) {
+    return ((uint64_t)lane63((uint32_t)(v >> 32)) << 32) | lane63((uint32_t)v);
+}
+__device__ __forceinline__ u128 lane63(u128 v) {
+    return ((u128)lane63((uint64_t)(v >> 64)) << 64) | lane63((uint64_t)v);
 }
 
 // ---------------------------------------------------------------------------
@@ -241,6 +299,8 @@ __device__ __forceinline__ JobDesc job_uniform(const JobDesc& J) {
     u.DP64 = uni(J.DP64);
     u.EP64 = uni(J.EP64);
     u.FH = uni(J.FH);
+    u.WP = uni(J.WP);
+    u.PO = uni(J.PO);
     u.pstart = uni(J.pstart);
     u.npack = uni(J.npack);
     u.sNL = uni(J.sNL);

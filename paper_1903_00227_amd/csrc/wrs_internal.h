@@ -64,6 +64,8 @@ struct JobDesc {
     uint64_t* DP64;       // [C+1] DP >> kshift (merge keys)
     uint64_t* EP64;       // [C+1] EP >> kshift
     int32_t* FH;          // [C+1] first heavy item in tiles >= c, -1 if none
+    float* WP;            // [C * TILE] each tile's weights, its lights then its heavies
+    uint16_t* PO;         // [C * TILE] offset inside the tile of each of those items
     int32_t* pstart;      // [npack] light events before each pack block's first event
     int32_t npack;        // pack blocks
     uint32_t* sNL;        // [nseg+1] segment totals / prefixes of the tile scan
