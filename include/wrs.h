@@ -138,6 +138,38 @@ int wrs_batch_status(const void* d_ws, int32_t njobs, void* stream, int* h_statu
  * 0: plain stream launches every call. */
 int wrs_batch_graph_mode(int enable);
 
+/* ---- launch-parameter tuning -------------------------------------------- */
+
+/* Two launch parameters are free and never change a result: the tile events
+ * each block of the merge handles (op WRS_TUNE_BUILD: 4, 8, 16 or 32) and the
+ * draws per sampler thread (op WRS_TUNE_SAMPLE: 1, 2, 4 or 8).  Tables and
+ * samples are bit-identical for every value; only speed differs.  A value is
+ * kept per device kind (architecture name and CU count) and size class:
+ * ceil(log2 n) for the build, ceil(log2 k) for the sampler.  A class without
+ * an entry uses a default derived from the size and the CU count.  At first
+ * use the library reads the JSON file named by the environment variable
+ * WRS_TUNE_FILE, if set.  The tables are per process and thread-safe. */
+enum { WRS_TUNE_BUILD = 1, WRS_TUNE_SAMPLE = 2 };
+
+/* Value in effect on the current device for `size` (n or k >= 1). */
+int wrs_tune_get(int op, int64_t size, int32_t* value);
+
+/* Set the value for the size class of `size` on the current device; 0 removes
+ * the entry (back to the default).  WRS_EINVAL for a value not listed above. */
+int wrs_tune_set(int op, int64_t size, int32_t value);
+
+/* Time every candidate on the current device and keep the fastest for the
+ * size class: WRS_TUNE_BUILD builds a table of n synthetic uniform weights,
+ * WRS_TUNE_SAMPLE draws k samples from such a table of n items.  Allocates
+ * and frees device memory (about 17 n + 4 k bytes) and synchronises `stream`;
+ * not for use inside stream capture.  *best (optional) receives the winner. */
+int wrs_autotune(int op, int64_t n, int64_t k, void* stream, int32_t* best);
+
+/* Write every entry to a JSON file, or merge the entries of such a file
+ * (entries for other devices are kept but not used on this one). */
+int wrs_tune_save(const char* path);
+int wrs_tune_load(const char* path);
+
 /* ---- serving -------------------------------------------------------------- */
 
 /* A request loop on one device: build requests create resident tables, sample

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libwrs.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EDEVICE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 OP_BUILD, OP_WOR = 1, 2
+TUNE_BUILD, TUNE_SAMPLE = 1, 2
 
 _lib = None
 
@@ -65,6 +66,12 @@ EXPORTS = {
     "wrs_batch_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_int)]),
     "wrs_batch_graph_mode": (ctypes.c_int, [ctypes.c_int]),
+    "wrs_tune_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
+    "wrs_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int32]),
+    "wrs_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_int32)]),
+    "wrs_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "wrs_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "wrs_serve_create": (ctypes.c_int, [ctypes.POINTER(ServeConfig), ctypes.POINTER(ctypes.c_void_p)]),
     "wrs_serve_submit_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                               ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
@@ -208,3 +215,29 @@ def batch_status(ws, njobs, stream=None):
 
 def batch_graph_mode(enable: bool):
     lib().wrs_batch_graph_mode(1 if enable else 0)
+
+
+# ---- launch-parameter tuning (result-neutral) ----
+
+def tune_get(op: int, size: int) -> int:
+    v = ctypes.c_int32()
+    _check("wrs_tune_get", lib().wrs_tune_get(op, size, ctypes.byref(v)))
+    return v.value
+
+
+def tune_set(op: int, size: int, value: int):
+    _check("wrs_tune_set", lib().wrs_tune_set(op, size, value))
+
+
+def autotune(op: int, n: int, k: int = 0, stream=None) -> int:
+    v = ctypes.c_int32()
+    _check("wrs_autotune", lib().wrs_autotune(op, n, k, _stream(stream), ctypes.byref(v)))
+    return v.value
+
+
+def tune_save(path: str):
+    _check("wrs_tune_save", lib().wrs_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    _check("wrs_tune_load", lib().wrs_tune_load(path.encode()))

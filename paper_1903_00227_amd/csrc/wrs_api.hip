@@ -69,19 +69,19 @@ extern "C" int wrs_alias_sample(const wrs_entry* d_table, int64_t n, uint64_t se
     if (n < 1 || n > N_MAX || k < 0) { set_error("wrs_alias_sample: bad n or k"); return WRS_EINVAL; }
     if (((uintptr_t)d_table) & 7) { set_error("wrs_alias_sample: table not 8-byte aligned"); return WRS_EINVAL; }
     if (k == 0) return WRS_OK;
-    if (cdiv(k, SAMPLES_PER_BLOCK) > 0x7fffffffLL) { set_error("wrs_alias_sample: k too large"); return WRS_EINVAL; }
     JobTable jt;
     memset(&jt, 0, sizeof jt);
     JobDesc& J = jt.one;
+    set_sample_job(J, k);
+    if (sample_blocks(J) > 0x7fffffffLL) { set_error("wrs_alias_sample: k too large"); return WRS_EINVAL; }
     J.table = const_cast<wrs_entry*>(d_table);
     J.n = n;
-    J.k = k;
     J.seed = seed;
     J.stream_id = stream_id;
     J.first_counter = first_counter;
     J.out = d_out;
     J.sc = nullptr;
-    hipError_t e = launch_sample(jt, cdiv(k, SAMPLES_PER_BLOCK), (hipStream_t)stream);
+    hipError_t e = launch_sample(jt, sample_blocks(J), (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail("wrs_alias_sample launch", e);
     return WRS_OK;
 }
@@ -204,7 +204,7 @@ static int batch_record(const wrs_job* h_jobs, int32_t njobs, void* d_ws, hipStr
         J.w = h_jobs[j].d_w;
         J.table = h_jobs[j].d_table;
         J.out = h_jobs[j].d_out;
-        J.k = h_jobs[j].k;
+        set_sample_job(J, h_jobs[j].k);
         J.seed = h_jobs[j].seed;
         J.stream_id = h_jobs[j].stream_id;
         J.first_counter = 0;
@@ -251,6 +251,8 @@ extern "C" int wrs_batch_build_sample(const wrs_job* h_jobs, int32_t njobs, void
     std::lock_guard<std::mutex> g(g_batch_mu);
     std::string key((const char*)h_jobs, sizeof(wrs_job) * njobs);
     key.append((const char*)&d_ws, sizeof d_ws);
+    const uint64_t gen = tuning_generation();
+    key.append((const char*)&gen, sizeof gen);
     if (g_graph_mode) {
         auto it = g_plans.find(key);
         if (it != g_plans.end()) {

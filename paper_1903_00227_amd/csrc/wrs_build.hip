@@ -21,7 +21,7 @@
 //   k_tileagg   per tile of 1024 items: #lights, light deficit, heavy excess
 //   k_scan_*    exclusive prefix over tiles (segmented)
 //   k_split     start event of every pack block (merge path over tile prefixes)
-//   k_pack      merge, cut at tile events, each block handling 16 events
+//   k_pack      merge, cut at tile events, each block handling 4..32 events
 //   k_sample    alias queries
 #include <float.h>
 #include <math.h>
@@ -42,7 +42,7 @@ struct BuildLayout {
     size_t sc, red, redinfo, NL, DP, EP, DP64, EP64, FH, WP, PO, pstart, sNL, sDP, sEP, sFH, total;
 };
 
-static int64_t pack_blocks(int64_t C) { return cdiv(2 * C, PACK_STEPS); }
+static int64_t pack_blocks(int64_t C, int32_t psteps) { return cdiv(2 * C, psteps); }
 
 static BuildLayout layout_for(int64_t n) {
     const int64_t C = cdiv(n, TILE);
@@ -61,7 +61,7 @@ static BuildLayout layout_for(int64_t n) {
     L.FH = o;      o = align256(o + sizeof(int32_t) * (C + 1));
     L.WP = o;      o = align256(o + sizeof(float) * C * TILE);
     L.PO = o;      o = align256(o + sizeof(uint16_t) * C * TILE);
-    L.pstart = o;  o = align256(o + sizeof(int32_t) * pack_blocks(C));
+    L.pstart = o;  o = align256(o + sizeof(int32_t) * pack_blocks(C, PACK_STEPS_MIN));
     L.sNL = o;     o = align256(o + sizeof(uint32_t) * (S + 1));
     L.sDP = o;     o = align256(o + sizeof(u128) * (S + 1));
     L.sEP = o;     o = align256(o + sizeof(u128) * (S + 1));
@@ -72,7 +72,7 @@ static BuildLayout layout_for(int64_t n) {
 
 size_t build_ws_bytes(int64_t n) { return layout_for(n).total; }
 
-void build_ws_layout(JobDesc& J, void* ws, int64_t n) {
+void build_ws_layout(JobDesc& J, void* ws, int64_t n, int32_t psteps) {
     const BuildLayout L = layout_for(n);
     char* b = (char*)ws;
     J.n = n;
@@ -91,7 +91,8 @@ void build_ws_layout(JobDesc& J, void* ws, int64_t n) {
     J.WP = (float*)(b + L.WP);
     J.PO = (uint16_t*)(b + L.PO);
     J.pstart = (int32_t*)(b + L.pstart);
-    J.npack = (int32_t)pack_blocks(J.ntiles);
+    J.psteps = psteps > 0 ? psteps : pack_steps_for(n);
+    J.npack = (int32_t)pack_blocks(J.ntiles, J.psteps);
     J.sNL = (uint32_t*)(b + L.sNL);
     J.sDP = (u128*)(b + L.sDP);
     J.sEP = (u128*)(b + L.sEP);
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(TPB) void k_split(JobTable jt) {
     const int64_t b = lb * TPB + threadIdx.x;
     if (b >= J.npack) return;
     const int64_t C = J.ntiles;
-    const int64_t s0 = b * PACK_STEPS;
+    const int64_t s0 = b * J.psteps;
     const WRS_GLOBAL uint64_t* DP = glb(J.DP64);
     const WRS_GLOBAL uint64_t* EP = glb(J.EP64);
     // largest x with: x == 0, or light event x precedes heavy event s0-x+1
@@ -647,11 +648,11 @@ struct PackShared {
     LightSlot A;
     HeavySlot B;
     uint64_t tmp[TPB / 64];
-    uint64_t dp[PACK_STEPS + 2];   // DP64[x0 + i]
-    uint64_t ep[PACK_STEPS + 2];   // EP64[y0 + i]
-    int32_t fh[PACK_STEPS + 2];    // FH[y0 + i]
-    uint32_t nlx[PACK_STEPS + 2];  // NL[x0 + i]
-    uint32_t nly[PACK_STEPS + 2];  // NL[y0 + i]
+    uint64_t dp[PACK_STEPS_MAX + 2];   // DP64[x0 + i]
+    uint64_t ep[PACK_STEPS_MAX + 2];   // EP64[y0 + i]
+    int32_t fh[PACK_STEPS_MAX + 2];    // FH[y0 + i]
+    uint32_t nlx[PACK_STEPS_MAX + 2];  // NL[x0 + i]
+    uint32_t nly[PACK_STEPS_MAX + 2];  // NL[y0 + i]
     int s_job;
 };
 
@@ -796,11 +797,12 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
     const BuildScalars sc = scalars_uniform(J.sc);
     const uint32_t n32 = (uint32_t)J.n;
     const int64_t C = J.ntiles;
-    const int64_t s0 = lb * PACK_STEPS;
-    const int64_t s1 = min(s0 + (int64_t)PACK_STEPS, 2 * C);
+    const int psteps = J.psteps;  // PACK_STEPS_MIN..PACK_STEPS_MAX
+    const int64_t s0 = lb * psteps;
+    const int64_t s1 = min(s0 + (int64_t)psteps, 2 * C);
     const int64_t x0 = glb(J.pstart)[lb];
     const int64_t y0 = s0 - x0;
-    for (int i = threadIdx.x; i < PACK_STEPS + 2; i += TPB) {
+    for (int i = threadIdx.x; i < psteps + 2; i += TPB) {
         const int64_t xi = x0 + i, yi = y0 + i;
         sh.dp[i] = (xi <= C) ? glb(J.DP64)[xi] : ~0ull;
         sh.ep[i] = (yi <= C) ? glb(J.EP64)[yi] : ~0ull;
@@ -975,30 +977,35 @@ __global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
     const uint64_t n = (uint64_t)J.n;
     const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
     const WRS_GLOBAL uint64_t* table = (const WRS_GLOBAL uint64_t*)glb(J.table);
-    const int64_t s0 = lb * SAMPLES_PER_BLOCK + threadIdx.x;
-    uint32_t r[SAMPLE_UNROLL];
-    float u[SAMPLE_UNROLL];
+    const int U = J.sunroll;  // 1..SAMPLE_UNROLL_MAX draws per thread
+    const int64_t s0 = lb * (int64_t)(SAMPLE_TPB * U) + threadIdx.x;
+    uint32_t r[SAMPLE_UNROLL_MAX];
+    float u[SAMPLE_UNROLL_MAX];
 #pragma unroll
-    for (int e = 0; e < SAMPLE_UNROLL; ++e) {
-        const int64_t s = s0 + (int64_t)e * SAMPLE_TPB;
-        const uint64_t c = J.first_counter + (uint64_t)s;
-        const uint4 x = philox4x32_10(make_uint4((uint32_t)c, (uint32_t)(c >> 32), J.stream_id, 0u), k0, k1);
-        // floor((x1 2^32 + x0) n / 2^64) for n < 2^31
-        const uint64_t lo = ((uint64_t)x.x * n) >> 32;
-        const uint64_t hi = (uint64_t)x.y * n + lo;
-        r[e] = (uint32_t)(hi >> 32);
-        u[e] = (float)(x.z >> 8) * (1.0f / 16777216.0f);
+    for (int e = 0; e < SAMPLE_UNROLL_MAX; ++e) {
+        if (e < U) {
+            const int64_t s = s0 + (int64_t)e * SAMPLE_TPB;
+            const uint64_t c = J.first_counter + (uint64_t)s;
+            const uint4 x = philox4x32_10(make_uint4((uint32_t)c, (uint32_t)(c >> 32), J.stream_id, 0u), k0, k1);
+            // floor((x1 2^32 + x0) n / 2^64) for n < 2^31
+            const uint64_t lo = ((uint64_t)x.x * n) >> 32;
+            const uint64_t hi = (uint64_t)x.y * n + lo;
+            r[e] = (uint32_t)(hi >> 32);
+            u[e] = (float)(x.z >> 8) * (1.0f / 16777216.0f);
+        }
     }
-    uint64_t ent[SAMPLE_UNROLL];
+    uint64_t ent[SAMPLE_UNROLL_MAX];
 #pragma unroll
-    for (int e = 0; e < SAMPLE_UNROLL; ++e) {
-        const int64_t s = s0 + (int64_t)e * SAMPLE_TPB;
-        ent[e] = (s < k) ? table[r[e]] : 0ull;  // cached: small tables stay in L2 / MALL
+    for (int e = 0; e < SAMPLE_UNROLL_MAX; ++e) {
+        if (e < U) {
+            const int64_t s = s0 + (int64_t)e * SAMPLE_TPB;
+            ent[e] = (s < k) ? table[r[e]] : 0ull;  // cached: small tables stay in L2 / MALL
+        }
     }
 #pragma unroll
-    for (int e = 0; e < SAMPLE_UNROLL; ++e) {
+    for (int e = 0; e < SAMPLE_UNROLL_MAX; ++e) {
         const int64_t s = s0 + (int64_t)e * SAMPLE_TPB;
-        if (s < k) {
+        if (e < U && s < k) {
             const float t = __uint_as_float((uint32_t)ent[e]);
             const int32_t a = (int32_t)(uint32_t)(ent[e] >> 32);
             glb(J.out)[s] = (u[e] < t) ? (int32_t)r[e] : a;
@@ -1009,6 +1016,15 @@ __global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
+void set_sample_job(JobDesc& J, int64_t k, int32_t sunroll) {
+    J.k = k;
+    J.sunroll = sunroll > 0 ? sunroll : sample_unroll_for(k);
+}
+
+int64_t sample_blocks(const JobDesc& J) {
+    return J.k > 0 ? cdiv(J.k, (int64_t)SAMPLE_TPB * J.sunroll) : 0;
+}
+
 void phase_blocks(const JobDesc& J, int64_t b[PH_COUNT]) {
     b[PH_RED] = J.nred;
     b[PH_FIN] = 1;
@@ -1017,7 +1033,7 @@ void phase_blocks(const JobDesc& J, int64_t b[PH_COUNT]) {
     b[PH_TOP] = 1;
     b[PH_SPLIT] = cdiv(J.npack, TPB);
     b[PH_PACK] = J.npack;
-    b[PH_SAMPLE] = cdiv(J.k, SAMPLES_PER_BLOCK);
+    b[PH_SAMPLE] = sample_blocks(J);
 }
 
 hipError_t launch_build(const JobTable& jt0, const int64_t* blocks, hipStream_t st) {

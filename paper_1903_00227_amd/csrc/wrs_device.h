@@ -277,6 +277,11 @@ __device__ __forceinline__ T* uni(T* p) {
     return (T*)uni((uint64_t)(uintptr_t)p);
 }
 
+// Every field is copied: a field added to JobDesc or BuildScalars must be
+// added here too (the size checks catch a forgotten one).
+static_assert(sizeof(JobDesc) == 216, "job_uniform copies every JobDesc field");
+static_assert(sizeof(BuildScalars) == 128, "scalars_uniform copies every BuildScalars field");
+
 __device__ __forceinline__ JobDesc job_uniform(const JobDesc& J) {
     JobDesc u;
     u.w = uni(J.w);
@@ -303,6 +308,8 @@ __device__ __forceinline__ JobDesc job_uniform(const JobDesc& J) {
     u.PO = uni(J.PO);
     u.pstart = uni(J.pstart);
     u.npack = uni(J.npack);
+    u.psteps = uni(J.psteps);
+    u.sunroll = uni(J.sunroll);
     u.sNL = uni(J.sNL);
     u.sDP = uni(J.sDP);
     u.sEP = uni(J.sEP);

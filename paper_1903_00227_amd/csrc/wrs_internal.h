@@ -16,12 +16,12 @@ constexpr int TILE = 1024;          // items per tile (classification and prefix
 constexpr int TILES_PER_AGG_BLOCK = 4;  // tile aggregation: one wave per tile
 constexpr int TPB = 256;            // threads per block of the tile kernels
 constexpr int IPT = TILE / TPB;     // items per thread in a tile
-constexpr int PACK_STEPS = 16;      // coarse tile events per pack block
+constexpr int PACK_STEPS_MIN = 4;   // tile events per pack block: tuned per size class
+constexpr int PACK_STEPS_MAX = 32;
 constexpr int RED_CHUNK = 65536;    // items per block of the total-weight reduction
 constexpr int SCAN_SEG = 2048;      // tiles per segment of the tile scan
 constexpr int SAMPLE_TPB = 256;     // threads per block of the sampler
-constexpr int SAMPLE_UNROLL = 8;    // draws per thread of the sampler
-constexpr int SAMPLES_PER_BLOCK = SAMPLE_TPB * SAMPLE_UNROLL;
+constexpr int SAMPLE_UNROLL_MAX = 8;  // draws per thread of the sampler: tuned per size class (1..8)
 
 // Per-table scalars written by the reduction, read by every later phase.
 struct alignas(16) BuildScalars {
@@ -68,6 +68,8 @@ struct JobDesc {
     uint16_t* PO;         // [C * TILE] offset inside the tile of each of those items
     int32_t* pstart;      // [npack] light events before each pack block's first event
     int32_t npack;        // pack blocks
+    int32_t psteps;       // tile events per pack block
+    int32_t sunroll;      // draws per sampler thread
     uint32_t* sNL;        // [nseg+1] segment totals / prefixes of the tile scan
     u128* sDP;
     u128* sEP;
@@ -89,7 +91,17 @@ struct JobTable {
 
 // Byte size of the per-table workspace and the pointer layout inside it.
 size_t build_ws_bytes(int64_t n);
-void build_ws_layout(JobDesc& J, void* ws, int64_t n);
+// psteps <= 0: the tuned (or default) value for n on the current device
+void build_ws_layout(JobDesc& J, void* ws, int64_t n, int32_t psteps = 0);
+void set_sample_job(JobDesc& J, int64_t k, int32_t sunroll = 0);
+int64_t sample_blocks(const JobDesc& J);
+
+// Launch parameters (result-neutral) for the current device: tuned values
+// when present, else defaults derived from the size and the CU count.
+int32_t pack_steps_for(int64_t n);
+int32_t sample_unroll_for(int64_t k);
+// Changes whenever a tuned value may have changed (recorded graphs keyed on it).
+uint64_t tuning_generation();
 
 // Blocks of every phase for one table (depends on n and k only).
 void phase_blocks(const JobDesc& J, int64_t blocks[PH_COUNT]);

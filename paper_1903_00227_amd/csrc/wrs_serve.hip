@@ -294,7 +294,7 @@ static bool issue(Server& S) {
             memset(&d[j], 0, sizeof(JobDesc));
             d[j].w = tb->d_w;
             d[j].table = tb->d_table;
-            d[j].k = 0;
+            set_sample_job(d[j], 0, 1);
             build_ws_layout(d[j], scratch[wsi++].first, tb->n);
             d[j].sc = tb->sc;
             int64_t b[PH_COUNT];
@@ -329,12 +329,12 @@ static bool issue(Server& S) {
             memset(&d[j], 0, sizeof(JobDesc));
             d[j].table = tb->d_table;
             d[j].n = tb->n;
-            d[j].k = smp[j]->k;
+            set_sample_job(d[j], smp[j]->k);
             d[j].seed = smp[j]->seed;
             d[j].stream_id = 0;
             d[j].out = smp[j]->d_out;
             d[j].sc = tb->sc;  // skips the draws if the build failed
-            off[(size_t)PH_SAMPLE * (ns + 1) + j + 1] = off[(size_t)PH_SAMPLE * (ns + 1) + j] + cdiv(smp[j]->k, SAMPLES_PER_BLOCK);
+            off[(size_t)PH_SAMPLE * (ns + 1) + j + 1] = off[(size_t)PH_SAMPLE * (ns + 1) + j] + sample_blocks(d[j]);
         }
         char* h = S.staging[slot] + bb;
         const size_t o_off = (sizeof(JobDesc) * ns + 255) & ~(size_t)255;
