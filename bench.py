@@ -8,9 +8,11 @@ Inputs are generated once and resident in HBM before the timed region.
 Printed: one JSON line.  `value` = alias build throughput (Gitems/s) over the
 step's builds; `sample_gsamples_s` = sampling throughput over the step's draws;
 `ms_per_step` = the whole step.  `roofline` covers the kernel with the largest
-share of the step (the sampler), `roofline_build` the split+pack kernel.  Extra
-objects report the batched (4096 tables) and served (Poisson trace) forms and
-the CPU oracle timed on the host.
+share of the step (the sampler); `build_hbm_frac_16B_floor` relates the build to
+its minimum HBM traffic.  Before timing, the library's autotuner picks the
+launch parameters of every size class the run uses (`tuning` lists them; they
+never change a result).  Extra objects report the batched (4096 tables) and
+served (Poisson trace) forms and the CPU oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -62,10 +64,11 @@ def main():
     ap.add_argument("--log2k", type=int, default=30)
     ap.add_argument("--skip-extras", action="store_true", help="only the main step (no batch/serve/cpu legs)")
     ap.add_argument("--profile-only", action="store_true", help="few steps, no extras (for rocprofv3)")
+    ap.add_argument("--no-tune", action="store_true", help="size-derived default launch parameters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the hot path has no multi-GPU form in this build "
-              "(see the sharding notes in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the hot path has no multi-GPU form; run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -87,6 +90,7 @@ def main():
     ws = wrs.new_workspace(wrs.OP_BUILD, n, 0, dev)
     out = torch.empty(k, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
+    tuning = tune(wrs, [n], [(n, k)], not args.no_tune and not args.profile_only)
 
     def step(timers=None):
         for fam in ("uniform", "power1"):
@@ -162,6 +166,7 @@ def main():
         "sample_gsamples_s": round(gsps, 3),
         "build_ms": {f: round(sum(v) / len(v), 4) for f, v in build_ms.items()},
         "sample_ms": {f: round(sum(v) / len(v), 4) for f, v in sample_ms.items()},
+        "tuning": tuning,
         "build_hbm_frac_16B_floor": round(build_gbs / HBM_PEAK_GBS, 4),
         "roofline": {"kernel": "k_sample", "bound": "hbm", "achieved": round(samp_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(samp_gbs / HBM_PEAK_GBS, 4),
@@ -170,7 +175,7 @@ def main():
     }
     if not args.skip_extras:
         result["without_replacement"] = bench_wor(wrs, torch, np, workloads)
-        result["batched"] = bench_batched(wrs, torch, np, workloads)
+        result["batched"] = bench_batched(wrs, torch, np, workloads, not args.no_tune)
         result["served"] = bench_served(wrs, torch, np, workloads)
         result["cpu_baseline"] = bench_cpu(np, workloads)
     print(json.dumps(result), flush=True)
@@ -203,11 +208,29 @@ def bench_wor(wrs, torch, np, workloads, reps=5):
     return res
 
 
-def bench_batched(wrs, torch, np, workloads):
+def tune(wrs, build_ns, sample_nks, run):
+    """Autotune (or just report) the launch parameters of the given size classes."""
+    res = {"tuned": bool(run), "build_events_per_block": {}, "sample_draws_per_thread": {}}
+    for n in build_ns:
+        if run:
+            wrs.autotune(wrs.TUNE_BUILD, n)
+        res["build_events_per_block"][f"2^{(n - 1).bit_length()}"] = wrs.tune_get(wrs.TUNE_BUILD, n)
+    for n, k in sample_nks:
+        if run:
+            wrs.autotune(wrs.TUNE_SAMPLE, n, k)
+        res["sample_draws_per_thread"][f"2^{(k - 1).bit_length()}"] = wrs.tune_get(wrs.TUNE_SAMPLE, k)
+    if run:
+        log("tuned:", res)
+    return res
+
+
+def bench_batched(wrs, torch, np, workloads, run_tune=True):
     """4096 tables (seed 4): one batched launch sequence replayed as a hipGraph,
     against one build + one sample call per table."""
     log("batched: preparing 4096 tables")
     jobs = workloads.batch_jobs(seed=4)
+    classes = sorted({(j["n"] - 1).bit_length() for j in jobs})
+    tuning = tune(wrs, [1 << c for c in classes], [(1 << c, 4 << c) for c in classes], run_tune)
     dev = torch.device("cuda:0")
     specs = []
     for j in jobs:
@@ -242,7 +265,7 @@ def bench_batched(wrs, torch, np, workloads):
     single_ms = e0.elapsed_time(e1)
     log(f"batched: fused {fused_ms:.3f} ms, one-at-a-time {single_ms:.3f} ms")
     return {"workload": "4096 tables, n_i log-uniform in [2^6,2^20], k_i = 4 n_i (seed 4)",
-            "items": items, "draws": draws, "fused_ms": round(fused_ms, 3),
+            "items": items, "draws": draws, "fused_ms": round(fused_ms, 3), "tuning": tuning,
             "one_at_a_time_ms": round(single_ms, 3), "speedup": round(single_ms / fused_ms, 2),
             "fused_gitems_s": round(items / (fused_ms * 1e-3) / 1e9, 3),
             "fused_hbm_frac_28B_per_item": round(28.0 * items / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
