@@ -8,9 +8,15 @@
 //                 expected count sum_i 1 - exp(-w_i tau), which is concave)
 //   k_wor_filter  Philox per item; since -ln(u) >= 1 - u, an item with
 //                 1 - u > tau w cannot have key <= tau and skips the logarithm;
-//                 survivors get the exact FP64 key and are appended if <= tau.
+//                 survivors are staged in LDS, get the exact FP64 key together
+//                 (one per lane, no divergence) and are appended if <= tau.
 //                 A second, predicated pass with tau = +inf runs only if fewer
-//                 than k candidates were found.
+//                 than k candidates were found.  Blocks reserve output slots
+//                 from 64 counters (block b uses counter b mod 64), each owning
+//                 its own region of the candidate arrays, so that no address
+//                 takes more than a few hundred atomics; k_wor_shards turns
+//                 the 64 counts into a prefix table, and later kernels address
+//                 candidate c through it.
 //   k_wor_hist / k_wor_find   radix-style select of the k-th smallest key over
 //                 the candidates: linear bins on the key, two levels of 16384
 //                 bins, until at most 8192 candidates share the target bin
@@ -31,6 +37,8 @@ constexpr int WOR_SMALL = 8192;                  // final in-LDS sort capacity
 constexpr int WOR_TAU_M = 4096;                  // subsample size for tau
 constexpr int WOR_WPB = WOR_TPB * 16;            // bitmap words per compaction block
 constexpr int WOR_CAND_TPB = 256;
+constexpr int WOR_SHARDS = 64;                   // candidate counters / regions
+constexpr int WOR_SHARD_STRIDE = 32;             // u64 words between counters (256 B)
 
 struct WorScalars {
     int32_t status;          // first word of the workspace, as for the build
@@ -42,7 +50,7 @@ struct WorScalars {
     double level_lo[WOR_NLEV];
     double level_scale[WOR_NLEV];
     unsigned long long maxkey_bits;
-    unsigned long long npos;
+    uint32_t prefix[2][WOR_SHARDS + 1];  // per pass: candidates in the shards before s
     int64_t k;
     int64_t rank;            // remaining 1-based rank inside the current bin
     int32_t level_bin[WOR_NLEV];
@@ -54,10 +62,16 @@ struct WorScalars {
 };
 
 struct WorLayout {
-    size_t sc, hist, small_key, small_idx, cand_key, cand_idx, bitmap, blk, total;
+    size_t sc, shard, hist, small_key, small_idx, cand_key, cand_idx, bitmap, blk, total;
 };
 
 static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Candidate slots per shard: every item of the shard's blocks.
+static inline int64_t wor_shard_cap(int64_t n) {
+    const int64_t fblocks = cdiv(n, (int64_t)WOR_TPB * WOR_IPT);
+    return cdiv(fblocks, (int64_t)WOR_SHARDS) * (WOR_TPB * WOR_IPT);
+}
 
 static WorLayout wor_layout(int64_t n) {
     WorLayout L;
@@ -65,11 +79,14 @@ static WorLayout wor_layout(int64_t n) {
     const int64_t nwords = cdiv(n, 32);
     const int64_t nblk = cdiv(nwords, WOR_WPB);
     L.sc = o;        o = a256(o + sizeof(WorScalars));
+    // per pass and shard: a counter and a max-key word, WOR_SHARD_STRIDE apart
+    L.shard = o;     o = a256(o + sizeof(unsigned long long) * 2 * 2 * WOR_SHARDS * WOR_SHARD_STRIDE);
     L.hist = o;      o = a256(o + sizeof(uint32_t) * WOR_NB * WOR_NLEV);
     L.small_key = o; o = a256(o + sizeof(double) * WOR_SMALL);
     L.small_idx = o; o = a256(o + sizeof(int32_t) * WOR_SMALL);
-    L.cand_key = o;  o = a256(o + sizeof(double) * n);
-    L.cand_idx = o;  o = a256(o + sizeof(int32_t) * n);
+    const int64_t cap = WOR_SHARDS * wor_shard_cap(n);
+    L.cand_key = o;  o = a256(o + sizeof(double) * cap);
+    L.cand_idx = o;  o = a256(o + sizeof(int32_t) * cap);
     L.bitmap = o;    o = a256(o + sizeof(uint32_t) * nwords);
     L.blk = o;       o = a256(o + sizeof(uint32_t) * (nblk + 1));
     L.total = o;
@@ -95,7 +112,13 @@ struct WorArgs {
     uint32_t* bitmap;
     uint32_t* blk;
     int64_t nwords;
+    unsigned long long* shard;  // [pass][counter | max key][shard * WOR_SHARD_STRIDE]
+    int64_t scap;               // candidate slots per shard
 };
+
+__device__ __forceinline__ unsigned long long* shard_word(const WorArgs& A, int pass, int what, int s) {
+    return A.shard + ((size_t)((pass - 1) * 2 + what) * WOR_SHARDS + s) * WOR_SHARD_STRIDE;
+}
 
 __device__ __forceinline__ uint32_t wor_x0(const WorArgs& A, int64_t i) {
     const uint4 x = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)((uint64_t)i >> 32), A.sid, 1u),
@@ -118,13 +141,13 @@ __global__ __launch_bounds__(1024) void k_wor_tau(WorArgs A) {
     WorScalars* S = A.S;
     // reset state (the whole select pipeline starts from here)
     for (int i = threadIdx.x; i < WOR_NB * WOR_NLEV; i += blockDim.x) A.hist[i] = 0;
+    for (int i = threadIdx.x; i < 2 * 2 * WOR_SHARDS; i += blockDim.x) A.shard[(size_t)i * WOR_SHARD_STRIDE] = 0;
     if (threadIdx.x == 0) {
         S->status = WRS_OK;
         S->bad = 0;
         S->count = 0;
         S->count2 = 0;
         S->maxkey_bits = 0;
-        S->npos = 0;
         S->k = A.k;
         S->rank = A.k;
         S->resolved = 0;
@@ -193,107 +216,161 @@ __global__ __launch_bounds__(1024) void k_wor_tau(WorArgs A) {
 // Candidates are staged in LDS per block (at most WOR_TPB * WOR_IPT of them)
 // and reserved in the output with one atomic per block.
 __global__ __launch_bounds__(WOR_TPB) void k_wor_filter(WorArgs A, int pass) {
-    __shared__ double s_key[WOR_TPB * WOR_IPT];
+    // Each wave stages, in its own region, the items that pass the prefilter:
+    // (index, x0 << 32 | weight bits); then, compacted in place, its
+    // candidates (index, key).
+    constexpr int WREG = 64 * WOR_IPT;  // staging entries per wave
+    __shared__ uint64_t s_key[WOR_TPB * WOR_IPT];
     __shared__ int32_t s_idx[WOR_TPB * WOR_IPT];
     __shared__ double s_max[WOR_TPB / 64];
-    __shared__ unsigned long long s_pos[WOR_TPB / 64];
     __shared__ uint32_t s_bad[WOR_TPB / 64];
-    __shared__ uint32_t s_cnt, s_base;
+    __shared__ uint32_t s_wc[WOR_TPB / 64];
+    __shared__ uint32_t s_base;
     WorScalars* S = A.S;
     if (pass == 2) {
         if (S->status != WRS_OK || (int64_t)S->count >= A.k) return;
     }
     const double tau = (pass == 2) ? (double)INFINITY : S->tau;
-    uint32_t* counter = (pass == 2) ? &S->count2 : &S->count;
+    const int shard = (int)(blockIdx.x % WOR_SHARDS);
     const int64_t n = A.n;
-    if (threadIdx.x == 0) s_cnt = 0;
     if (pass == 1) {  // clear this block's share of the bitmap
         const int64_t per = cdiv(A.nwords, (int64_t)gridDim.x);
         const int64_t w0 = (int64_t)blockIdx.x * per;
         const int64_t w1 = min(A.nwords, w0 + per);
         for (int64_t i = w0 + threadIdx.x; i < w1; i += WOR_TPB) A.bitmap[i] = 0u;
     }
-    __syncthreads();
     const int lane = threadIdx.x & 63;
-    double kmax = 0.0;
+    const int wv = threadIdx.x >> 6;
+    const int wbase = wv * WREG;
     uint32_t bad = 0;
-    unsigned long long pos = 0;
     const int64_t base = (int64_t)blockIdx.x * (WOR_TPB * WOR_IPT);
+    // Phase 1, per item: domain check, Philox, and the prefilter 1 - u <= tau w
+    // (a key -ln(u) / w <= tau implies it since -ln(u) >= 1 - u).  Survivors are
+    // staged; the logarithm waits for phase 2, where every lane has one.
+    uint32_t nst = 0;  // staged by this wave (the same in all its lanes)
 #pragma unroll 2
     for (int e = 0; e < WOR_IPT; ++e) {
         const int64_t i = base + (int64_t)e * WOR_TPB + threadIdx.x;
-        bool cand = false;
-        double key = 0.0;
+        bool pre = false;
+        uint32_t x0 = 0;
+        float v = 0.0f;
         if (i < n) {
-            const float v = A.w[i];
+            v = A.w[i];
             bad |= (uint32_t)(!(v >= 0.0f) || isinf(v));
             if (v > 0.0f && !isinf(v)) {
-                ++pos;
-                const uint32_t x0 = wor_x0(A, i);
+                x0 = wor_x0(A, i);
                 const double omu = (double)(0xFFFFFFFFu - x0) * (1.0 / 4294967296.0);  // 1 - u
-                if (omu <= tau * (double)v * (1.0 + 1e-12)) {
-                    key = neg_log_u(x0) / (double)v;
-                    cand = key <= tau;
-                }
+                pre = omu <= tau * (double)v * (1.0 + 1e-12);
             }
+        }
+        const unsigned long long mask = __ballot(pre);
+        if (pre) {
+            const uint32_t p = wbase + nst + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            s_key[p] = ((uint64_t)x0 << 32) | __float_as_uint(v);
+            s_idx[p] = (int32_t)i;
+        }
+        nst += (uint32_t)__popcll(mask);
+    }
+    // Phase 2 (per wave): keys of the staged items, 64 at a time, and an
+    // ordered compaction of the candidates (key <= tau) in place.  A lane's
+    // output slot is at or below its input slot, and the wave's LDS accesses
+    // run in program order, so no entry is overwritten before it is read.
+    double kmax = 0.0;
+    uint32_t nc = 0;  // this wave's candidates
+    for (uint32_t r0 = 0; r0 < nst; r0 += 64) {
+        const uint32_t c = r0 + lane;
+        bool cand = false;
+        double key = 0.0;
+        int32_t idx = 0;
+        if (c < nst) {
+            const uint64_t st = s_key[wbase + c];
+            idx = s_idx[wbase + c];
+            const float v = __uint_as_float((uint32_t)st);
+            key = neg_log_u((uint32_t)(st >> 32)) / (double)v;
+            cand = key <= tau;
         }
         const unsigned long long mask = __ballot(cand);
-        if (mask) {
-            const uint32_t cnt = (uint32_t)__popcll(mask);
-            const int leader = __ffsll((long long)mask) - 1;
-            uint32_t b = 0;
-            if (lane == leader) b = atomicAdd(&s_cnt, cnt);
-            b = __shfl(b, leader, 64);
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-            if (cand) {
-                s_key[b + rank] = key;
-                s_idx[b + rank] = (int32_t)i;
-                kmax = fmax(kmax, key);
-            }
+        if (cand) {
+            const uint32_t p = wbase + nc + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            s_key[p] = (uint64_t)__double_as_longlong(key);
+            s_idx[p] = idx;
+            kmax = fmax(kmax, key);
         }
+        nc += (uint32_t)__popcll(mask);
     }
     for (int off = 32; off >= 1; off >>= 1) {
         kmax = fmax(kmax, __shfl_xor(kmax, off, 64));
         bad |= __shfl_xor(bad, off, 64);
-        pos += __shfl_xor(pos, off, 64);
     }
-    const int wv = threadIdx.x >> 6;
     if (lane == 0) {
         s_max[wv] = kmax;
         s_bad[wv] = bad;
-        s_pos[wv] = pos;
+        s_wc[wv] = nc;
     }
     __syncthreads();
-    const uint32_t nc = s_cnt;
     if (threadIdx.x == 0) {
-        s_base = nc ? atomicAdd(counter, nc) : 0u;
-        for (int k = 1; k < WOR_TPB / 64; ++k) {
+        uint32_t tot = 0;
+        for (int k = 0; k < WOR_TPB / 64; ++k) {
             kmax = fmax(kmax, s_max[k]);
             bad |= s_bad[k];
+            tot += s_wc[k];
         }
-        kmax = fmax(kmax, s_max[0]);
-        bad |= s_bad[0];
-        if (kmax > 0.0) atomicMax(&S->maxkey_bits, (unsigned long long)__double_as_longlong(kmax));
-        if (pass == 1) {
-            if (bad) atomicOr(&S->bad, 1u);
-            atomicAdd(&S->npos, (unsigned long long)(s_pos[0] + s_pos[1] + s_pos[2] + s_pos[3]));
-        }
+        s_base = tot ? (uint32_t)atomicAdd(shard_word(A, pass, 0, shard), (unsigned long long)tot) : 0u;
+        if (kmax > 0.0) atomicMax(shard_word(A, pass, 1, shard), (unsigned long long)__double_as_longlong(kmax));
+        if (pass == 1 && bad) atomicOr(&S->bad, 1u);
     }
     __syncthreads();
-    const uint32_t b0 = s_base;
-    for (uint32_t c = threadIdx.x; c < nc; c += WOR_TPB) {
-        const uint32_t p = b0 + c;
-        if ((int64_t)p < n) {
-            A.ckey[p] = s_key[c];
-            A.cidx[p] = s_idx[c];
-        }
+    // this block's slots: shard region + reserved offset + earlier waves
+    int64_t b0 = (int64_t)shard * A.scap + s_base;
+    for (int k = 0; k < wv; ++k) b0 += s_wc[k];
+    for (uint32_t c = lane; c < nc; c += 64) {
+        const int64_t p = b0 + c;  // < (shard + 1) * scap: the shard's blocks hold at most scap items
+        A.ckey[p] = __longlong_as_double((long long)s_key[wbase + c]);
+        A.cidx[p] = s_idx[wbase + c];
+    }
+}
+
+// After a filter pass: candidates per shard -> prefix table, total, max key.
+__global__ __launch_bounds__(WOR_SHARDS) void k_wor_shards(WorArgs A, int pass) {
+    WorScalars* S = A.S;
+    if (pass == 2 && (S->status != WRS_OK || (int64_t)S->count >= A.k)) return;
+    const int s = threadIdx.x;  // one wave, one lane per shard
+    const uint32_t c = (uint32_t)*shard_word(A, pass, 0, s);
+    const unsigned long long m = *shard_word(A, pass, 1, s);
+    const uint32_t incl = wave_incl_scan(c);
+    S->prefix[pass - 1][s] = incl - c;
+    unsigned long long mx = m;
+    for (int off = 32; off >= 1; off >>= 1) mx = max(mx, (unsigned long long)__shfl_xor(mx, off, 64));
+    if (s == WOR_SHARDS - 1) {
+        S->prefix[pass - 1][WOR_SHARDS] = incl;
+        if (pass == 1) S->count = incl; else S->count2 = incl;
+        S->maxkey_bits = max(S->maxkey_bits, mx);  // non-negative doubles order as their bits
     }
 }
 
 // Number of candidates of the pass that holds the answer.
 __device__ __forceinline__ uint32_t wor_ncand(const WorScalars* S) {
     return ((int64_t)S->count >= S->k) ? S->count : S->count2;
+}
+
+// Candidate c (0 <= c < wor_ncand) of the pass in use lives in shard s, the
+// largest with P[s] <= c, at slot s * scap + c - P[s].  P is the pass's prefix
+// table, copied to LDS by every block (all threads, then a barrier).
+__device__ __forceinline__ void load_cand_map(const WorScalars* S, uint32_t* P) {
+    const int pass = ((int64_t)S->count >= S->k) ? 0 : 1;
+    for (int i = threadIdx.x; i <= WOR_SHARDS; i += blockDim.x) P[i] = S->prefix[pass][i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ int64_t cand_slot(const uint32_t* P, int64_t scap, uint32_t c) {
+    int lo = 0, hi = WOR_SHARDS - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    return (int64_t)lo * scap + (c - P[lo]);
 }
 
 __device__ __forceinline__ int wor_bin(double key, double lo, double scale) {
@@ -310,10 +387,12 @@ __device__ __forceinline__ bool wor_in_set(const WorScalars* S, double key, int 
 
 __global__ __launch_bounds__(WOR_CAND_TPB) void k_wor_hist(WorArgs A, int level) {
     __shared__ uint32_t h[WOR_NB];
+    __shared__ uint32_t P[WOR_SHARDS + 1];
     WorScalars* S = A.S;
     if (S->status != WRS_OK || S->resolved || S->bad) return;
     const uint32_t nc = wor_ncand(S);
     if ((int64_t)nc < A.k) return;
+    load_cand_map(S, P);
     double lo, scale;
     if (level == 0) {
         const double mx = __longlong_as_double((long long)S->maxkey_bits);
@@ -330,7 +409,7 @@ __global__ __launch_bounds__(WOR_CAND_TPB) void k_wor_hist(WorArgs A, int level)
     for (int i = threadIdx.x; i < WOR_NB; i += WOR_CAND_TPB) h[i] = 0;
     __syncthreads();
     for (int64_t c = (int64_t)blockIdx.x * WOR_CAND_TPB + threadIdx.x; c < nc; c += (int64_t)gridDim.x * WOR_CAND_TPB) {
-        const double key = A.ckey[c];
+        const double key = A.ckey[cand_slot(P, A.scap, (uint32_t)c)];
         if (level == 0 || wor_in_set(S, key, level)) atomicAdd(&h[wor_bin(key, lo, scale)], 1u);
     }
     __syncthreads();
@@ -380,17 +459,39 @@ __global__ __launch_bounds__(1024) void k_wor_find(WorArgs A, int level) {
 }
 
 __global__ __launch_bounds__(WOR_CAND_TPB) void k_wor_gather(WorArgs A) {
+    __shared__ uint32_t P[WOR_SHARDS + 1];
     WorScalars* S = A.S;
     if (S->status != WRS_OK || !S->resolved) return;
     const uint32_t nc = wor_ncand(S);
     const int nlev = S->nlev;
-    for (int64_t c = (int64_t)blockIdx.x * WOR_CAND_TPB + threadIdx.x; c < nc; c += (int64_t)gridDim.x * WOR_CAND_TPB) {
-        const double key = A.ckey[c];
-        if (wor_in_set(S, key, nlev)) {
-            const uint32_t p = atomicAdd(&S->small_count, 1u);
-            if (p < (uint32_t)WOR_SMALL) {
-                A.skey[p] = key;
-                A.sidx[p] = A.cidx[c];
+    load_cand_map(S, P);
+    const int lane = threadIdx.x & 63;
+    // every lane of the block runs the same number of iterations (the ballot needs the whole wave)
+    const int64_t stride = (int64_t)gridDim.x * WOR_CAND_TPB;
+    for (int64_t c0 = (int64_t)blockIdx.x * WOR_CAND_TPB; c0 < nc; c0 += stride) {
+        const int64_t c = c0 + threadIdx.x;
+        bool in = false;
+        double key = 0.0;
+        int64_t q = 0;
+        if (c < nc) {
+            q = cand_slot(P, A.scap, (uint32_t)c);
+            key = A.ckey[q];
+            in = wor_in_set(S, key, nlev);
+        }
+        // one atomic per wave
+        const unsigned long long mask = __ballot(in);
+        if (mask) {
+            const int leader = __ffsll((long long)mask) - 1;
+            uint32_t b = 0;
+            if (lane == leader) b = atomicAdd(&S->small_count, (uint32_t)__popcll(mask));
+            b = __shfl(b, leader, 64);
+            if (in) {
+                const uint32_t p = b + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                if (p < (uint32_t)WOR_SMALL) {
+                    A.skey[p] = key;
+                    A.sidx[p] = A.cidx[q];
+                }
             }
         }
     }
@@ -448,14 +549,17 @@ __global__ __launch_bounds__(1024) void k_wor_final(WorArgs A) {
 }
 
 __global__ __launch_bounds__(WOR_CAND_TPB) void k_wor_mark(WorArgs A) {
+    __shared__ uint32_t P[WOR_SHARDS + 1];
     WorScalars* S = A.S;
     if (S->status != WRS_OK) return;
     const uint32_t nc = wor_ncand(S);
     const double kk = S->kkey;
     const int32_t ki = S->kidx;
+    load_cand_map(S, P);
     for (int64_t c = (int64_t)blockIdx.x * WOR_CAND_TPB + threadIdx.x; c < nc; c += (int64_t)gridDim.x * WOR_CAND_TPB) {
-        const double key = A.ckey[c];
-        const int32_t idx = A.cidx[c];
+        const int64_t q = cand_slot(P, A.scap, (uint32_t)c);
+        const double key = A.ckey[q];
+        const int32_t idx = A.cidx[q];
         if (key < kk || (key == kk && idx <= ki)) atomicOr(&A.bitmap[idx >> 5], 1u << (idx & 31));
     }
 }
@@ -565,13 +669,17 @@ int launch_wor(const float* w, int64_t n, int64_t k, uint64_t seed, uint32_t sid
     A.bitmap = (uint32_t*)(b + L.bitmap);
     A.blk = (uint32_t*)(b + L.blk);
     A.nwords = cdiv(n, 32);
+    A.shard = (unsigned long long*)(b + L.shard);
+    A.scap = wor_shard_cap(n);
     const int64_t fblocks = cdiv(n, (int64_t)WOR_TPB * WOR_IPT);
     const int nblk = (int)cdiv(A.nwords, WOR_WPB);
     // candidate kernels: enough blocks to fill the chip, few enough for cheap atomics
     const int cblocks = 512;
     hipLaunchKernelGGL(k_wor_tau, dim3(1), dim3(1024), 0, st, A);
     hipLaunchKernelGGL(k_wor_filter, dim3((unsigned)fblocks), dim3(WOR_TPB), 0, st, A, 1);
+    hipLaunchKernelGGL(k_wor_shards, dim3(1), dim3(WOR_SHARDS), 0, st, A, 1);
     hipLaunchKernelGGL(k_wor_filter, dim3((unsigned)fblocks), dim3(WOR_TPB), 0, st, A, 2);
+    hipLaunchKernelGGL(k_wor_shards, dim3(1), dim3(WOR_SHARDS), 0, st, A, 2);
     for (int l = 0; l < WOR_NLEV; ++l) {
         hipLaunchKernelGGL(k_wor_hist, dim3(cblocks), dim3(WOR_CAND_TPB), 0, st, A, l);
         hipLaunchKernelGGL(k_wor_find, dim3(1), dim3(1024), 0, st, A, l);
