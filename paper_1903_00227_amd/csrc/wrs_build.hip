@@ -971,7 +971,9 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
 __global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
     __shared__ int s_job;
     int64_t lb;
-    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
+    // XCD-contiguous block order: a job's blocks share one or two L2s, so a
+    // small table stays in the L2 of the XCDs that sample it
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job, xcd_contiguous_block()));
     if (J.sc != nullptr && J.sc->status != WRS_OK) return;
     const int64_t k = J.k;
     const uint64_t n = (uint64_t)J.n;
