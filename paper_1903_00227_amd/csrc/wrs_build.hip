@@ -785,8 +785,13 @@ __device__ __forceinline__ void store_entry(wrs_entry* table, int64_t item, floa
     *(WRS_GLOBAL vuint2*)(table + item) = v;
 }
 
-__device__ __forceinline__ float light_t(float w, const BuildScalars& sc) {
-    return (float)((double)w * sc.nscale * sc.rQ);
+// A light's bucket keeps t = n w / W; lscale = n 2^-G / Q.
+__device__ __forceinline__ float light_t(float w, double lscale) { return (float)((double)w * lscale); }
+
+// A heavy's bucket keeps t = 1 + (E - D) / W, from a key difference.
+__device__ __forceinline__ float heavy_t(uint64_t E, uint64_t D, double tscale) {
+    const float t = (float)fma((double)(int64_t)(E - D), tscale, 1.0);
+    return fminf(fmaxf(t, 0.0f), 1.0f);
 }
 
 __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
@@ -842,6 +847,7 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
         }
     }
     const double tscale = sc.tscale;
+    const double lscale = sc.nscale * sc.rQ;
     const LightSlot& A = sh.A;
     const HeavySlot& B = sh.B;
     for (int64_t s = s0; s < s1; ++s) {
@@ -880,12 +886,8 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
             for (int d = threadIdx.x; d < nlc; d += TPB) {
                 const int lp = pl + d;
                 const int64_t own = abase + A.off[lp];
-                float t = light_t(A.w[lp], sc);
-                int32_t a2 = al;
-                if (!hv && al == FH_NONE) {
-                    a2 = (int32_t)own;
-                    t = fminf(t, 1.0f);
-                }
+                const float t = fminf(light_t(A.w[lp], lscale), 1.0f);
+                const int32_t a2 = (!hv && al == FH_NONE) ? (int32_t)own : al;
                 store_entry(J.table, own, t, a2);
             }
         } else if (nlc == 0 && nhc > 0) {
@@ -893,8 +895,7 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
             const uint64_t Dn = (pl < nlx) ? A.key[pl] : Dend;
             for (int d = threadIdx.x; d < nhc; d += TPB) {
                 const int hp = ph + d;
-                float t = (float)(1.0 + (double)(int64_t)(B.key[hp] - Dn) * tscale);
-                t = fminf(fmaxf(t, 0.0f), 1.0f);
+                const float t = heavy_t(B.key[hp], Dn, tscale);
                 const int64_t own = bbase + B.off[hp];
                 const int32_t al = (hp + 1 < nhy) ? (int32_t)(bbase + B.off[hp + 1])
                                                   : (nextH != FH_NONE ? nextH : (int32_t)own);
@@ -913,35 +914,33 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                     if (ok) jlo = mid; else jhi = mid - 1;
                 }
                 int j = jlo, i = d0 - jlo;
+                // keys at the two cursors: the next heavy of the cell, and the
+                // next light of the tile (Dend past the tile's last light)
+                uint64_t kb = (j < nhc) ? B.key[ph + j] : ~0ull;
+                uint64_t ka = (pl + i < nlx) ? A.key[pl + i] : Dend;
+                // One body for both kinds of bucket (the lanes of a wave
+                // disagree on the kind, so branches would run both ways):
+                // a light aliases the next heavy not yet emitted (ph + j), a
+                // heavy the one after it.
                 for (int d = d0; d < d1; ++d) {
-                    const bool take_h = (j < nhc) && (i >= nlc || B.key[ph + j] <= A.key[pl + i]);
+                    const bool take_h = (j < nhc) && (i >= nlc || kb <= ka);
+                    const int ia = min(pl + i, TILE - 1), ib = min(ph + j, TILE - 1);
+                    const int64_t own = take_h ? bbase + B.off[ib] : abase + A.off[ia];
+                    const int q = ph + j + (take_h ? 1 : 0);
+                    const int32_t al = (q < nhy) ? (int32_t)(bbase + B.off[q])
+                                                 : (nextH != FH_NONE ? nextH : (int32_t)own);
+                    const float t = take_h ? heavy_t(kb, ka, tscale) : fminf(light_t(A.w[ia], lscale), 1.0f);
+                    store_entry(J.table, own, t, al);
                     if (take_h) {
-                        const int hp = ph + j;
-                        const uint64_t E = B.key[hp];
-                        const uint64_t Dn = (pl + i < nlx) ? A.key[pl + i] : Dend;
-                        float t = (float)(1.0 + (double)(int64_t)(E - Dn) * tscale);
-                        t = fminf(fmaxf(t, 0.0f), 1.0f);
-                        const int64_t own = bbase + B.off[hp];
-                        const int32_t al = (hp + 1 < nhy) ? (int32_t)(bbase + B.off[hp + 1])
-                                                          : (nextH != FH_NONE ? nextH : (int32_t)own);
-                        store_entry(J.table, own, t, al);
                         ++j;
                     } else {
-                        const int lp = pl + i;
-                        const int64_t own = abase + A.off[lp];
-                        float t = light_t(A.w[lp], sc);
-                        int32_t al;
-                        if (ph + j < nhy) {
-                            al = (int32_t)(bbase + B.off[ph + j]);
-                        } else if (nextH != FH_NONE) {
-                            al = nextH;
-                        } else {
-                            al = (int32_t)own;
-                            t = fminf(t, 1.0f);
-                        }
-                        store_entry(J.table, own, t, al);
                         ++i;
                     }
+                    // one LDS read: the key at the cursor that moved
+                    const bool more = take_h ? (j < nhc) : (pl + i < nlx);
+                    const uint64_t nk = more ? (take_h ? B.key[ph + j] : A.key[pl + i]) : (take_h ? ~0ull : Dend);
+                    kb = take_h ? nk : kb;
+                    ka = take_h ? ka : nk;
                 }
             }
         }
