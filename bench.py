@@ -173,6 +173,12 @@ def main():
                      "traffic": load_traffic("k_sample"),
                      "algorithmic_bytes_per_launch": samp_bytes},
     }
+    traffic = result["roofline"]["traffic"]
+    if traffic:
+        # bytes the counters saw move (whole 128-byte lines per random gather), per second
+        tgbs = traffic / (samp_avg_ms * 1e-3) / 1e9
+        result["roofline"]["traffic_gbs"] = round(tgbs, 1)
+        result["roofline"]["traffic_frac"] = round(tgbs / HBM_PEAK_GBS, 4)
     if not args.skip_extras:
         result["without_replacement"] = bench_wor(wrs, torch, np, workloads)
         result["batched"] = bench_batched(wrs, torch, np, workloads, not args.no_tune)
