@@ -163,14 +163,23 @@ static BatchHeader batch_header(int32_t njobs) {
 }
 
 struct BatchPlan {
-    std::vector<char> key;           // descriptors + workspace address
+    std::vector<char> blob;          // the descriptors the graph's kernels read from the workspace
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
+    uint64_t last_use = 0;
 };
 
+static constexpr size_t MAX_PLANS = 64;  // recorded graphs kept; the least recently used goes first
 static std::mutex g_batch_mu;
 static std::unordered_map<std::string, BatchPlan*> g_plans;
+static uint64_t g_plan_clock = 0;
 static bool g_graph_mode = true;
+
+static void destroy_plan(BatchPlan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+}
 
 }  // namespace wrs
 
@@ -256,7 +265,14 @@ extern "C" int wrs_batch_build_sample(const wrs_job* h_jobs, int32_t njobs, void
     if (g_graph_mode) {
         auto it = g_plans.find(key);
         if (it != g_plans.end()) {
-            hipError_t e = hipGraphLaunch(it->second->exec, st);
+            // The workspace may hold another batch's descriptors since the
+            // recording: upload this batch's again, ahead of the replay on the
+            // same stream (the plan owns the host copy).
+            BatchPlan* plan = it->second;
+            plan->last_use = ++g_plan_clock;
+            hipError_t e = hipMemcpyAsync(d_ws, plan->blob.data(), plan->blob.size(), hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) return dev_fail("upload batch descriptors", e);
+            e = hipGraphLaunch(plan->exec, st);
             if (e != hipSuccess) return dev_fail("hipGraphLaunch", e);
             return WRS_OK;
         }
@@ -294,6 +310,18 @@ extern "C" int wrs_batch_build_sample(const wrs_job* h_jobs, int32_t njobs, void
     if (le != hipSuccess || e != hipSuccess) { delete plan; return dev_fail("batch capture", le != hipSuccess ? le : e); }
     e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) { (void)hipGraphDestroy(plan->graph); delete plan; return dev_fail("hipGraphInstantiate", e); }
+    plan->blob = std::move(blob);
+    plan->last_use = ++g_plan_clock;
+    if (g_plans.size() >= MAX_PLANS) {
+        // a graph may still run on some stream: wait before destroying one
+        auto old = g_plans.begin();
+        for (auto i = g_plans.begin(); i != g_plans.end(); ++i)
+            if (i->second->last_use < old->second->last_use) old = i;
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) { destroy_plan(plan); return dev_fail("batch graph cache", e); }
+        destroy_plan(old->second);
+        g_plans.erase(old);
+    }
     g_plans[key] = plan;
     e = hipGraphLaunch(plan->exec, st);
     if (e != hipSuccess) return dev_fail("hipGraphLaunch", e);

@@ -48,7 +48,7 @@ def test_batch_equals_single_calls(wrs, graph):
     ws = torch.empty(wrs.batch_workspace_bytes(arr), dtype=torch.uint8, device="cuda:0")
     wrs.batch_graph_mode(graph)
     say("batch", len(jobs), "graph" if graph else "stream")
-    for rep in range(2):  # second call replays the recorded graph
+    for rep in range(4):  # later calls replay the recorded graph, with eager work in between
         for s in specs:
             s["table"].fill_(-1)
             s["out"].fill_(-1)
@@ -61,6 +61,32 @@ def test_batch_equals_single_calls(wrs, graph):
             assert np.array_equal(s["table"].cpu().numpy(), tab), (rep, i)
             assert np.array_equal(s["out"][:s["k"]].cpu().numpy(), smp), (rep, i)
     wrs.batch_graph_mode(True)
+
+
+def test_batch_graphs_share_a_workspace(wrs):
+    """Two different batches alternate on one workspace: replaying the first
+    batch's recorded graph must use its own descriptors again."""
+    import torch
+    ja = workloads.batch_jobs(seed=11, count=40, lo_log2=4, hi_log2=15)
+    jb = workloads.batch_jobs(seed=12, count=7, lo_log2=10, hi_log2=16)
+    sa, sb = make_batch(wrs, ja), make_batch(wrs, jb)
+    aa, ab = wrs.make_jobs(sa), wrs.make_jobs(sb)
+    nb = max(wrs.batch_workspace_bytes(aa), wrs.batch_workspace_bytes(ab))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+    wrs.batch_graph_mode(True)
+    for step, (arr, specs) in enumerate([(aa, sa), (ab, sb), (aa, sa), (ab, sb), (aa, sa)]):
+        say("shared workspace, call", step)
+        for s in specs:
+            s["table"].fill_(-1)
+            s["out"].fill_(-1)
+        wrs.batch_build_sample(arr, ws)
+        torch.cuda.synchronize()
+        assert all(st == wrs.OK for st in wrs.batch_status(ws, len(specs)))
+        for i in range(0, len(specs), 3):
+            s = specs[i]
+            tab, smp = single(wrs, s["w"], s["n"], s["k"], 4, s["stream_id"])
+            assert np.array_equal(s["table"].cpu().numpy(), tab), (step, i)
+            assert np.array_equal(s["out"][:s["k"]].cpu().numpy(), smp), (step, i)
 
 
 def test_batch_reports_bad_job(wrs):
