@@ -1060,6 +1060,18 @@ hipError_t launch_build(const JobTable& jt0, const int64_t* blocks, hipStream_t 
     return hipSuccess;
 }
 
+// Status word of every job of a job table, gathered into d_dst[0..njobs).
+__global__ __launch_bounds__(TPB) void k_collect_status(JobTable jt, int32_t* d_dst) {
+    for (int j = (int)(blockIdx.x * TPB + threadIdx.x); j < jt.njobs; j += (int)(gridDim.x * TPB))
+        d_dst[j] = jt.jobs[j].sc->status;
+}
+
+hipError_t launch_collect_status(const JobTable& jt, int32_t* d_dst, hipStream_t st) {
+    if (jt.njobs < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_collect_status, dim3((unsigned)cdiv(jt.njobs, TPB)), dim3(TPB), 0, st, jt, d_dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_sample(const JobTable& jt0, int64_t blocks, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
     JobTable jt = jt0;

@@ -109,6 +109,8 @@ void phase_blocks(const JobDesc& J, int64_t blocks[PH_COUNT]);
 // Host launchers (stream-ordered).
 hipError_t launch_build(const JobTable& jt, const int64_t* blocks, hipStream_t st);
 hipError_t launch_sample(const JobTable& jt, int64_t blocks, hipStream_t st);
+// jt.jobs[j].sc->status -> d_dst[j] for every job (device memory, jobs on the device)
+hipError_t launch_collect_status(const JobTable& jt, int32_t* d_dst, hipStream_t st);
 
 // WOR
 size_t wor_ws_bytes(int64_t n, int64_t k);

@@ -115,6 +115,7 @@ struct Request {
     double t_submit = 0, t_done = 0;
     int status = WRS_OK;
     bool done = false;
+    int build_index = -1;  // position among the builds of its batch
 };
 
 struct Batch {
@@ -122,6 +123,7 @@ struct Batch {
     hipEvent_t ev;
     std::vector<Request*> reqs;
     std::vector<std::pair<void*, size_t>> scratch;  // pool memory to give back
+    const int32_t* h_status = nullptr;  // build statuses, copied to the slot's pinned buffer by the batch
 };
 
 struct Server {
@@ -155,6 +157,8 @@ static size_t descriptor_bytes(int njobs) {
     return o;
 }
 
+static size_t status_bytes(int njobs) { return ((size_t)sizeof(int32_t) * njobs + 255) & ~(size_t)255; }
+
 static void finish_request(Server& S, Request* r, int status, double t) {
     r->status = status;
     r->done = true;
@@ -180,12 +184,7 @@ static void retire(Server& S, bool block) {
             Table* tb = (it != S.tables.end()) ? it->second.get() : nullptr;
             int st = (q == hipSuccess) ? WRS_OK : WRS_EDEVICE;
             if (r->op == OP_BUILD && tb) {
-                if (st == WRS_OK) {
-                    int32_t dev_status = WRS_OK;
-                    if (hipMemcpy(&dev_status, &tb->sc->status, sizeof dev_status, hipMemcpyDeviceToHost) != hipSuccess)
-                        dev_status = WRS_EDEVICE;
-                    st = dev_status;
-                }
+                if (st == WRS_OK) st = b.h_status ? b.h_status[r->build_index] : WRS_EDEVICE;
                 tb->state = (st == WRS_OK) ? T_READY : T_FAILED;
                 tb->status = st;
             }
@@ -268,7 +267,8 @@ static bool issue(Server& S) {
     // descriptors: builds first, then samples, each its own job table
     const int nb = (int)bld.size(), ns = (int)smp.size();
     const size_t bb = nb ? descriptor_bytes(nb) : 0, sb = ns ? descriptor_bytes(ns) : 0;
-    const size_t need_stage = bb + sb;
+    const size_t stb = nb ? status_bytes(nb) : 0;  // build statuses, device -> pinned host
+    const size_t need_stage = bb + sb + stb;
     if (S.staging_bytes[slot] < need_stage) {
         if (S.staging[slot]) (void)hipHostFree(S.staging[slot]);
         S.staging[slot] = nullptr;
@@ -319,7 +319,13 @@ static bool issue(Server& S) {
             Table* tb = S.tables[bld[j]->table_id].get();
             if (!tb->ready) (void)hipEventCreateWithFlags(&tb->ready, hipEventDisableTiming);
             (void)hipEventRecord(tb->ready, st);
+            bld[j]->build_index = j;
         }
+        // statuses for retire(): gathered on the device, one copy to the pinned buffer
+        int32_t* d_st = (int32_t*)(dev_desc + bb + sb);
+        int32_t* h_st = (int32_t*)(S.staging[slot] + bb + sb);
+        ok = ok && launch_collect_status(jt, d_st, st) == hipSuccess;
+        ok = ok && hipMemcpyAsync(h_st, d_st, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st) == hipSuccess;
     }
     if (ok && ns) {
         std::vector<JobDesc> d(ns);
@@ -353,6 +359,7 @@ static bool issue(Server& S) {
     b.slot = slot;
     b.reqs = take;
     b.scratch = scratch;
+    b.h_status = (ok && nb) ? (const int32_t*)(S.staging[slot] + bb + sb) : nullptr;
     (void)hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
     (void)hipEventRecord(b.ev, st);
     if (!ok) {
