@@ -139,6 +139,8 @@ __device__ __forceinline__ void block_reduce_dd(double& hi, double& lo, uint32_t
     }
 }
 
+__device__ void finalize_scalars(const JobDesc& J, double hi, double lo, uint32_t bad, uint32_t pos);
+
 __global__ __launch_bounds__(TPB) void k_reduce(JobTable jt) {
     __shared__ int s_job;
     __shared__ double s_hi[TPB / 64], s_lo[TPB / 64];
@@ -169,6 +171,9 @@ __global__ __launch_bounds__(TPB) void k_reduce(JobTable jt) {
         J.red[lb] = make_double2(hi, lo);
         J.redinfo[2 * lb] = bad;
         J.redinfo[2 * lb + 1] = pos;
+        // a single block holds the whole total: finalize here (k_finalize gets
+        // no block for this job; the scalars are the same bits either way)
+        if (J.nred == 1) finalize_scalars(J, hi, lo, bad, pos);
     }
 }
 
@@ -180,22 +185,9 @@ __device__ __forceinline__ u128 u128_from_integral_double(double d) {
 }
 
 // a1 (second half): combine partials in a fixed order, derive the grid.
-__global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
-    __shared__ int s_job;
-    __shared__ double s_hi[TPB / 64], s_lo[TPB / 64];
-    __shared__ uint32_t s_bad[TPB / 64], s_pos[TPB / 64];
-    int64_t lb;
-    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
-    double hi = 0.0, lo = 0.0;
-    uint32_t bad = 0, pos = 0;
-    for (int r = threadIdx.x; r < J.nred; r += TPB) {
-        const double2 p = J.red[r];
-        dd_add(hi, lo, p.x, p.y);
-        bad |= J.redinfo[2 * r];
-        pos += J.redinfo[2 * r + 1];
-    }
-    block_reduce_dd(hi, lo, bad, pos, s_hi, s_lo, s_bad, s_pos);
-    if (threadIdx.x != 0) return;
+// Grid exponent G, integer capacity Q and the derived scalars, from the total
+// weight hi + lo (double-double) and the domain flags; one thread.
+__device__ void finalize_scalars(const JobDesc& J, double hi, double lo, uint32_t bad, uint32_t pos) {
     BuildScalars S;
     S.status = WRS_OK;
     S.npos = pos;
@@ -257,6 +249,24 @@ __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
         S.wthr = lo;
     }
     *J.sc = S;
+}
+
+__global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
+    __shared__ int s_job;
+    __shared__ double s_hi[TPB / 64], s_lo[TPB / 64];
+    __shared__ uint32_t s_bad[TPB / 64], s_pos[TPB / 64];
+    int64_t lb;
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
+    double hi = 0.0, lo = 0.0;
+    uint32_t bad = 0, pos = 0;
+    for (int r = threadIdx.x; r < J.nred; r += TPB) {
+        const double2 p = J.red[r];
+        dd_add(hi, lo, p.x, p.y);
+        bad |= J.redinfo[2 * r];
+        pos += J.redinfo[2 * r + 1];
+    }
+    block_reduce_dd(hi, lo, bad, pos, s_hi, s_lo, s_bad, s_pos);
+    if (threadIdx.x == 0) finalize_scalars(J, hi, lo, bad, pos);
 }
 
 // ---------------------------------------------------------------------------
@@ -475,6 +485,10 @@ __global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
         suf = min(suf, fh[e]);
         fh[e] = suf;
     }
+    // The only segment: its prefixes are final, so this block also writes the
+    // 64-bit keys and the totals (k_scan_top and k_scan_fix get no blocks).
+    const bool single = J.nseg == 1;
+    const int ks = uni(J.sc->kshift);
 #pragma unroll
     for (int e = 0; e < SEG_PER_THREAD; ++e) {
         const int64_t c = t0 + e;
@@ -483,6 +497,10 @@ __global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
             J.DP[c] = dp_ex;
             J.EP[c] = ep_ex;
             J.FH[c] = fh[e];
+            if (single) {
+                J.DP64[c] = (uint64_t)(dp_ex >> ks);
+                J.EP64[c] = (uint64_t)(ep_ex >> ks);
+            }
         }
         nl_ex += nl[e];
         dp_ex += dp[e];
@@ -493,6 +511,16 @@ __global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
         J.sDP[lb] = dp_tot;
         J.sEP[lb] = ep_tot;
         J.sFH[lb] = min(fmin, later);  // thread 0 holds the first tiles: the segment minimum
+    }
+    if (single) {
+        if (threadIdx.x == 0) {
+            J.NL[C] = nl_tot;
+            J.DP[C] = dp_tot;
+            J.EP[C] = ep_tot;
+            J.DP64[C] = (uint64_t)(dp_tot >> ks);
+            J.EP64[C] = (uint64_t)(ep_tot >> ks);
+            J.FH[C] = FH_NONE;
+        }
     }
 }
 
@@ -1028,10 +1056,12 @@ int64_t sample_blocks(const JobDesc& J) {
 
 void phase_blocks(const JobDesc& J, int64_t b[PH_COUNT]) {
     b[PH_RED] = J.nred;
-    b[PH_FIN] = 1;
+    b[PH_FIN] = J.nred > 1 ? 1 : 0;  // one reduction block finalizes in place
     b[PH_TILE] = cdiv(J.ntiles, TILES_PER_AGG_BLOCK);
     b[PH_SEG] = J.nseg;
-    b[PH_TOP] = 1;
+    // one segment: k_scan_seg finishes the scan itself
+    b[PH_TOP] = J.nseg > 1 ? 1 : 0;
+    b[PH_FIX] = J.nseg > 1 ? J.nseg : 0;
     b[PH_SPLIT] = cdiv(J.npack, TPB);
     b[PH_PACK] = J.npack;
     b[PH_SAMPLE] = sample_blocks(J);
@@ -1053,7 +1083,7 @@ hipError_t launch_build(const JobTable& jt0, const int64_t* blocks, hipStream_t 
     WRS_LAUNCH(k_tileagg, PH_TILE);
     WRS_LAUNCH(k_scan_seg, PH_SEG);
     WRS_LAUNCH(k_scan_top, PH_TOP);
-    WRS_LAUNCH(k_scan_fix, PH_SEG);
+    WRS_LAUNCH(k_scan_fix, PH_FIX);
     WRS_LAUNCH(k_split, PH_SPLIT);
     WRS_LAUNCH(k_pack, PH_PACK);
 #undef WRS_LAUNCH

@@ -76,7 +76,7 @@ struct JobDesc {
     int32_t* sFH;
 };
 
-enum Phase { PH_RED = 0, PH_FIN, PH_TILE, PH_SEG, PH_TOP, PH_SPLIT, PH_PACK, PH_SAMPLE, PH_COUNT };
+enum Phase { PH_RED = 0, PH_FIN, PH_TILE, PH_SEG, PH_TOP, PH_FIX, PH_SPLIT, PH_PACK, PH_SAMPLE, PH_COUNT };
 
 // A launch covers one phase of one job (jobs == nullptr, description in `one`)
 // or of many jobs (device array `jobs`, with block offsets per phase in
