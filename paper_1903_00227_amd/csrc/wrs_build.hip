@@ -18,11 +18,15 @@
 // Phases (one launch each, all jobs of a batch share every launch):
 //   k_reduce    W as a double-double, weight domain check
 //   k_finalize  grid exponent G and integer capacity Q = round(W / 2^G)
-//   k_tileagg   per tile of 1024 items: #lights, light deficit, heavy excess
+//   k_tileagg   per tile of 1024 items: #lights, light deficit, heavy excess,
+//               and the tile rewritten lights first, then heavies
 //   k_scan_*    exclusive prefix over tiles (segmented)
 //   k_split     start event of every pack block (merge path over tile prefixes)
 //   k_pack      merge, cut at tile events, each block handling 4..32 events
 //   k_sample    alias queries
+// A job with one reduction block (n <= 65536) finalizes inside k_reduce, and a
+// job with one scan segment (n <= 2^21) finishes the scan and the split inside
+// k_scan_seg; such jobs add no block to the launches they skip.
 #include <float.h>
 #include <math.h>
 #include <stdio.h>
@@ -441,6 +445,24 @@ __device__ __forceinline__ int block_suffix_min_excl(int v, int* s_w) {
     return min(excl_in_wave, later);
 }
 
+// Light events before pack block b's first event (the paper's split(), on
+// tile prefixes): the largest x with x == 0, or light event x before heavy
+// event s0 - x + 1, where s0 = b * psteps.  Needs DP64 and EP64.
+__device__ __forceinline__ int32_t pack_start(const JobDesc& J, int64_t b) {
+    const int64_t C = J.ntiles;
+    const int64_t s0 = b * J.psteps;
+    const WRS_GLOBAL uint64_t* DP = glb(J.DP64);
+    const WRS_GLOBAL uint64_t* EP = glb(J.EP64);
+    int64_t lo = max((int64_t)0, s0 - C), hi = min(s0, C);
+    while (lo < hi) {
+        const int64_t x = (lo + hi + 1) >> 1;
+        const int64_t y1 = s0 - x + 1;
+        const bool ok = (y1 > C) || (x < C && DP[x] < EP[y1]);
+        if (ok) lo = x; else hi = x - 1;
+    }
+    return (int32_t)lo;
+}
+
 __global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
     __shared__ int s_job;
     __shared__ ScanTmp tmp;
@@ -521,6 +543,9 @@ __global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
             J.EP64[C] = (uint64_t)(ep_tot >> ks);
             J.FH[C] = FH_NONE;
         }
+        // every key is written (and visible to the block): the pack starts too
+        __syncthreads();
+        for (int64_t b = threadIdx.x; b < J.npack; b += TPB) glb(J.pstart)[b] = pack_start(J, b);
     }
 }
 
@@ -642,19 +667,7 @@ __global__ __launch_bounds__(TPB) void k_split(JobTable jt) {
     if (J.sc->status != WRS_OK) return;
     const int64_t b = lb * TPB + threadIdx.x;
     if (b >= J.npack) return;
-    const int64_t C = J.ntiles;
-    const int64_t s0 = b * J.psteps;
-    const WRS_GLOBAL uint64_t* DP = glb(J.DP64);
-    const WRS_GLOBAL uint64_t* EP = glb(J.EP64);
-    // largest x with: x == 0, or light event x precedes heavy event s0-x+1
-    int64_t lo = max((int64_t)0, s0 - C), hi = min(s0, C);
-    while (lo < hi) {
-        const int64_t x = (lo + hi + 1) >> 1;
-        const int64_t y1 = s0 - x + 1;
-        const bool ok = (y1 > C) || (x < C && DP[x] < EP[y1]);
-        if (ok) lo = x; else hi = x - 1;
-    }
-    glb(J.pstart)[b] = (int32_t)lo;
+    glb(J.pstart)[b] = pack_start(J, b);
 }
 
 // The two sides of the merge staged in LDS: the lights of tile x with the
@@ -1062,7 +1075,7 @@ void phase_blocks(const JobDesc& J, int64_t b[PH_COUNT]) {
     // one segment: k_scan_seg finishes the scan itself
     b[PH_TOP] = J.nseg > 1 ? 1 : 0;
     b[PH_FIX] = J.nseg > 1 ? J.nseg : 0;
-    b[PH_SPLIT] = cdiv(J.npack, TPB);
+    b[PH_SPLIT] = J.nseg > 1 ? cdiv(J.npack, TPB) : 0;
     b[PH_PACK] = J.npack;
     b[PH_SAMPLE] = sample_blocks(J);
 }
