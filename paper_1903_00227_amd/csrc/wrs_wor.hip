@@ -419,7 +419,7 @@ __global__ __launch_bounds__(WOR_CAND_TPB) void k_wor_hist(WorArgs A, int level)
 }
 
 __global__ __launch_bounds__(1024) void k_wor_find(WorArgs A, int level) {
-    __shared__ uint32_t part[1024];
+    __shared__ uint32_t wsum[1024 / 64];
     WorScalars* S = A.S;
     if (threadIdx.x == 0) {
         // domain checks once every candidate pass is complete
@@ -429,16 +429,22 @@ __global__ __launch_bounds__(1024) void k_wor_find(WorArgs A, int level) {
     __syncthreads();
     if (S->status != WRS_OK || S->resolved) return;
     const uint32_t* g = A.hist + (size_t)level * WOR_NB;
-    constexpr int PER = WOR_NB / 1024;
+    constexpr int PER = WOR_NB / 1024;  // consecutive bins per thread
+    const int t = threadIdx.x;
     uint32_t local = 0;
-    for (int e = 0; e < PER; ++e) local += g[threadIdx.x * PER + e];
-    part[threadIdx.x] = local;
+    for (int e = 0; e < PER; ++e) local += g[t * PER + e];
+    // block scan of the per-thread counts: wave scans, then the wave totals
+    const uint32_t winc = wave_incl_scan(local);
+    if ((t & 63) == 63) wsum[t >> 6] = winc;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t rank = S->rank;
-        int64_t cum = 0;
-        int t = 0;
-        while (t < 1023 && cum + part[t] < rank) cum += part[t++];
+    uint32_t before = 0;
+    for (int w = 0; w < (t >> 6); ++w) before += wsum[w];
+    const int64_t excl = (int64_t)before + winc - local, incl = excl + local;
+    // the one thread whose bins hold the rank-th key (the last thread if the
+    // counts fall short, which the checks above rule out)
+    const int64_t rank = S->rank;
+    if ((excl < rank && rank <= incl) || (t == 1023 && rank > incl)) {
+        int64_t cum = excl;
         int b = t * PER;
         while (b < (t + 1) * PER - 1 && cum + g[b] < rank) cum += g[b++];
         const uint32_t cnt = g[b];
