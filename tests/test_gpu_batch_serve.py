@@ -169,3 +169,85 @@ def test_serve_alone_vs_mix(wrs):
             si += 1
     assert stats.completed == len(reqs) and stats.failed == 0
     assert stats.bytes_peak <= 8 << 30
+
+
+def test_serve_failures_are_contained(wrs):
+    """A build with a NaN weight fails (and so do draws from its table), the
+    other requests still complete with the single-call results; oversized
+    builds, unknown tables and released tables are refused at submission."""
+    import ctypes
+    import torch
+    L = wrs.lib()
+    cfg = wrs.ServeConfig(256 << 20, 16, 0, 2)
+    srv = ctypes.c_void_p()
+    assert L.wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.OK
+    try:
+        tid, rid, st = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int()
+        bad = torch.from_numpy(workloads.uniform(5000, 8)).to("cuda:0")
+        bad[1234] = float("nan")
+        good = torch.from_numpy(workloads.power_law(70000, 1.0, 9)).to("cuda:0")
+        say("serve: bad build, good build, draws from both")
+        assert L.wrs_serve_submit_build(srv, bad.data_ptr(), bad.numel(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
+        t_bad, r_bad = tid.value, rid.value
+        assert L.wrs_serve_submit_build(srv, good.data_ptr(), good.numel(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
+        t_good, r_good = tid.value, rid.value
+        o_bad = torch.full((1000,), -1, dtype=torch.int32, device="cuda:0")
+        o_good = torch.full((30000,), -1, dtype=torch.int32, device="cuda:0")
+        assert L.wrs_serve_submit_sample(srv, t_bad, 1000, 3, o_bad.data_ptr(), ctypes.byref(rid)) == wrs.OK
+        r_sbad = rid.value
+        assert L.wrs_serve_submit_sample(srv, t_good, 30000, 4, o_good.data_ptr(), ctypes.byref(rid)) == wrs.OK
+        r_sgood = rid.value
+        for r, want in ((r_bad, wrs.EDOMAIN), (r_good, wrs.OK), (r_sbad, wrs.EDOMAIN), (r_sgood, wrs.OK)):
+            assert L.wrs_serve_wait(srv, r, ctypes.byref(st)) == wrs.OK
+            assert st.value == want, (r, st.value)
+        _, smp = single(wrs, good, good.numel(), 30000, 4, 0)
+        assert np.array_equal(o_good.cpu().numpy(), smp)
+        assert bool((o_bad == -1).all())  # nothing drawn from a failed table
+        # refused at submission
+        huge = torch.empty(1, dtype=torch.float32, device="cuda:0")
+        assert L.wrs_serve_submit_build(srv, huge.data_ptr(), 1 << 28, ctypes.byref(tid), ctypes.byref(rid)) == wrs.ENOMEM
+        assert L.wrs_serve_submit_sample(srv, 987654321, 10, 1, o_bad.data_ptr(), ctypes.byref(rid)) == wrs.ENOTFOUND
+        assert L.wrs_serve_release_table(srv, t_good) == wrs.OK
+        assert L.wrs_serve_submit_sample(srv, t_good, 10, 1, o_bad.data_ptr(), ctypes.byref(rid)) == wrs.ENOTFOUND
+        s = wrs.ServeStats()
+        assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
+        assert s.completed == 4 and s.failed == 2
+    finally:
+        L.wrs_serve_destroy(srv)
+
+
+def test_serve_evicts_idle_tables_within_budget(wrs):
+    """Tables whose total exceeds the budget: idle ones are evicted (least
+    recently used first), the device pool never exceeds the budget, and the
+    newest table still serves draws equal to single calls."""
+    import ctypes
+    import torch
+    L = wrs.lib()
+    # a resident table of 2^20 items takes 8 MB; a build also needs ~6.5 MB of
+    # workspace until it retires: from the fourth build on, old tables must go
+    budget = 32 << 20
+    cfg = wrs.ServeConfig(budget, 8, 0, 2)
+    srv = ctypes.c_void_p()
+    assert L.wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.OK
+    try:
+        tid, rid, st = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int()
+        ws_, tids = [], []
+        for i in range(6):
+            w = torch.from_numpy(workloads.uniform(1 << 20, 60 + i)).to("cuda:0")
+            ws_.append(w)
+            say("serve under a tight budget: build", i)
+            assert L.wrs_serve_submit_build(srv, w.data_ptr(), w.numel(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
+            tids.append(tid.value)
+            assert L.wrs_serve_wait(srv, rid.value, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
+        out = torch.full((50000,), -1, dtype=torch.int32, device="cuda:0")
+        assert L.wrs_serve_submit_sample(srv, tids[-1], 50000, 7, out.data_ptr(), ctypes.byref(rid)) == wrs.OK
+        assert L.wrs_serve_wait(srv, rid.value, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
+        _, smp = single(wrs, ws_[-1], 1 << 20, 50000, 7, 0)
+        assert np.array_equal(out.cpu().numpy(), smp)
+        s = wrs.ServeStats()
+        assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
+        assert s.bytes_peak <= budget and s.tables_resident < 6 and s.failed == 0
+        # the oldest table went first
+        assert L.wrs_serve_submit_sample(srv, tids[0], 10, 1, out.data_ptr(), ctypes.byref(rid)) == wrs.ENOTFOUND
+    finally:
+        L.wrs_serve_destroy(srv)
