@@ -49,6 +49,8 @@ def _load():
         "orc_total_weight": (ctypes.c_int, [P, i64, P, P]),
         "orc_vose_build": (ctypes.c_int, [P, i64, P, P]),
         "orc_sweep_build": (ctypes.c_int, [P, i64, P, P]),
+        "orc_psaplus_build": (ctypes.c_int, [P, i64, i64, P, P]),
+        "orc_psaplus_leftovers": (ctypes.c_int64, [P, i64, i64]),
         "orc_ratio_f32": (ctypes.c_float, [ctypes.c_float, u32, ctypes.c_float, u32]),
         "orc_light_t_at": (ctypes.c_int, [P, i64, P, i64, P, P]),
         "orc_alias_sample": (ctypes.c_int, [P, P, i64, u64, u32, u64, i64, P]),
@@ -112,6 +114,26 @@ def sweep_build(w):
     a = np.empty(w.size, np.int32)
     _check("orc_sweep_build", _load().orc_sweep_build(_ptr(w), w.size, _ptr(t), _ptr(a)))
     return t, a
+
+
+def psaplus_build(w, block):
+    """Section 4.2.1 (PSA+): the sweep inside consecutive blocks of `block`
+    items until a block runs out of lights or heavies, then the sweep over all
+    items left, in exact arithmetic -> (t float32[n], alias int32[n])."""
+    w = _f32(w)
+    t = np.empty(w.size, np.float32)
+    a = np.empty(w.size, np.int32)
+    _check("orc_psaplus_build", _load().orc_psaplus_build(_ptr(w), w.size, int(block), _ptr(t), _ptr(a)))
+    return t, a
+
+
+def psaplus_leftovers(w, block) -> int:
+    """How many items the greedy blocks of psaplus_build leave over."""
+    w = _f32(w)
+    r = int(_load().orc_psaplus_leftovers(_ptr(w), w.size, int(block)))
+    if r < 0:
+        raise OracleError("orc_psaplus_leftovers", r)
+    return r
 
 
 def ratio_f32(wa, ma, wb, mb) -> np.float32:

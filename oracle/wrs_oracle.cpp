@@ -19,6 +19,8 @@
  *   orc_sweep_build     the sweeping construction, Algorithm 2 (Section 4.1), in
  *                       exact arithmetic.  The parallel splitting algorithm of
  *                       Section 4.2 (Algorithm 3) produces exactly this table.
+ *   orc_psaplus_build   greedy assignment inside blocks, then the sweep over the
+ *                       items left (Section 4.2.1, PSA+), in exact arithmetic.
  *   orc_alias_sample*   alias queries (Section 2.2, last paragraph; branchless
  *                       select of Section 10), one Philox call per draw.
  *   orc_reconstruct     per-item mass implied by a table (alias-table definition,
@@ -397,6 +399,158 @@ extern "C" int orc_sweep_build(const float* w, int64_t n, float* t, int32_t* ali
         i = next_light(i + 1);
     }
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 4.2.1: greedy assignment by blocks, then the splitting algorithm  */
+/* on what is left (PSA+).  Items are cut into consecutive blocks of `block` */
+/* items.  Inside each block the sweep of Algorithm 2 runs on the block's own */
+/* lights and heavies and stops as soon as it needs a light or a next heavy   */
+/* that the block does not have.  Everything it packed is final.  The items   */
+/* not packed go on, in index order, to a second sweep over all blocks'        */
+/* leftovers; the parallel splitting algorithm (Algorithm 3) computes exactly */
+/* that sweep, since it only skips the finished items.                        */
+/* Reading: the heavy the block stopped at enters the second sweep with the   */
+/* part of its size not yet placed (its bucket is not filled yet), as a heavy */
+/* if that part exceeds W and as a light otherwise; the untouched items keep  */
+/* their sizes.  The second sweep uses the readings of orc_sweep_build.       */
+/* ------------------------------------------------------------------------- */
+static void sweep_list(const std::vector<int64_t>& idx, const std::vector<xnum>& size, const xnum* W,
+                       float* t, int32_t* alias) {
+    const size_t m = idx.size();
+    std::vector<unsigned char> is_light(m);
+    for (size_t k = 0; k < m; ++k) is_light[k] = x_cmp(&size[k], W) <= 0;
+    auto next_light = [&](size_t from) { while (from < m && !is_light[from]) ++from; return from; };
+    auto next_heavy = [&](size_t from) { while (from < m && is_light[from]) ++from; return from; };
+    size_t i = next_light(0), j = next_heavy(0);
+    xnum r;
+    if (j < m) r = size[j];
+    while (j < m) {
+        if (x_cmp(&r, W) > 0) {
+            if (i >= m) abort();  /* the leftovers fill whole buckets: cannot happen */
+            t[idx[i]] = x_ratio_to_f32(&size[i], W);
+            alias[idx[i]] = (int32_t)idx[j];
+            x_add(&r, &size[i]);
+            x_sub(&r, W);
+            i = next_light(i + 1);
+        } else {
+            t[idx[j]] = x_ratio_to_f32(&r, W);
+            const size_t jn = next_heavy(j + 1);
+            alias[idx[j]] = (int32_t)idx[jn < m ? jn : j];
+            if (jn < m) {
+                x_add(&r, &size[jn]);
+                x_sub(&r, W);
+            }
+            j = jn;
+        }
+    }
+    while (i < m) {
+        float tf = x_ratio_to_f32(&size[i], W);
+        t[idx[i]] = tf > 1.0f ? 1.0f : tf;
+        alias[idx[i]] = (int32_t)idx[i];
+        i = next_light(i + 1);
+    }
+}
+
+extern "C" int orc_psaplus_build(const float* w, int64_t n, int64_t block, float* t, int32_t* alias) {
+    if (!w || !t || !alias || n < 1 || n > 2147483647LL || block < 1) return ORC_EINVAL;
+    if (!valid_weights(w, n)) return ORC_EDOMAIN;
+    xnum W;
+    exact_sum(w, n, &W);
+    if (x_is_zero(&W)) return ORC_EDOMAIN;
+    const uint32_t nn = (uint32_t)n;
+    std::vector<int64_t> left_idx;
+    std::vector<xnum> left_size;
+    for (int64_t b0 = 0; b0 < n; b0 += block) {
+        const int64_t b1 = std::min(n, b0 + block);
+        std::vector<xnum> s((size_t)(b1 - b0));
+        std::vector<unsigned char> light((size_t)(b1 - b0));
+        for (int64_t i = b0; i < b1; ++i) {
+            x_from_float_times(&s[i - b0], w[i], nn);
+            light[i - b0] = x_cmp(&s[i - b0], &W) <= 0;
+        }
+        auto next_light = [&](int64_t from) { while (from < b1 && !light[from - b0]) ++from; return from; };
+        auto next_heavy = [&](int64_t from) { while (from < b1 && light[from - b0]) ++from; return from; };
+        std::vector<std::pair<int64_t, xnum>> left;
+        int64_t i = next_light(b0), j = next_heavy(b0);
+        if (j >= b1) {                    /* no heavy in the block: every light is left */
+            for (; i < b1; i = next_light(i + 1)) left.push_back({i, s[i - b0]});
+        } else {
+            xnum r = s[j - b0];
+            while (true) {
+                if (x_cmp(&r, &W) > 0) {
+                    if (i >= b1) {        /* out of lights: j (part placed) and later heavies are left */
+                        left.push_back({j, r});
+                        for (int64_t h = next_heavy(j + 1); h < b1; h = next_heavy(h + 1)) left.push_back({h, s[h - b0]});
+                        break;
+                    }
+                    t[i] = x_ratio_to_f32(&s[i - b0], &W);
+                    alias[i] = (int32_t)j;
+                    x_add(&r, &s[i - b0]);
+                    x_sub(&r, &W);
+                    i = next_light(i + 1);
+                } else {
+                    const int64_t jn = next_heavy(j + 1);
+                    if (jn >= b1) {       /* out of heavies: j (rest below W) and later lights are left */
+                        left.push_back({j, r});
+                        for (; i < b1; i = next_light(i + 1)) left.push_back({i, s[i - b0]});
+                        break;
+                    }
+                    t[j] = x_ratio_to_f32(&r, &W);
+                    alias[j] = (int32_t)jn;
+                    x_add(&r, &s[jn - b0]);
+                    x_sub(&r, &W);
+                    j = jn;
+                }
+            }
+        }
+        std::sort(left.begin(), left.end(),
+                  [](const std::pair<int64_t, xnum>& a, const std::pair<int64_t, xnum>& b) { return a.first < b.first; });
+        for (auto& e : left) {
+            left_idx.push_back(e.first);
+            left_size.push_back(e.second);
+        }
+    }
+    sweep_list(left_idx, left_size, &W, t, alias);
+    return ORC_OK;
+}
+
+/* Number of items the greedy blocks of orc_psaplus_build leave to the second
+   sweep (a diagnostic of the same construction). */
+extern "C" int64_t orc_psaplus_leftovers(const float* w, int64_t n, int64_t block) {
+    if (!w || n < 1 || n > 2147483647LL || block < 1) return ORC_EINVAL;
+    if (!valid_weights(w, n)) return ORC_EDOMAIN;
+    xnum W;
+    exact_sum(w, n, &W);
+    if (x_is_zero(&W)) return ORC_EDOMAIN;
+    const uint32_t nn = (uint32_t)n;
+    int64_t total = 0;
+    for (int64_t b0 = 0; b0 < n; b0 += block) {
+        const int64_t b1 = std::min(n, b0 + block);
+        std::vector<xnum> L, H;
+        for (int64_t i = b0; i < b1; ++i) {
+            xnum s;
+            x_from_float_times(&s, w[i], nn);
+            if (x_cmp(&s, &W) <= 0) L.push_back(s); else H.push_back(s);
+        }
+        if (H.empty() || L.empty()) { total += (int64_t)(L.size() + H.size()); continue; }
+        size_t i = 0, j = 0;
+        xnum r = H[0];
+        while (true) {
+            if (x_cmp(&r, &W) > 0) {
+                if (i >= L.size()) { total += (int64_t)(H.size() - j); break; }
+                x_add(&r, &L[i]);
+                x_sub(&r, &W);
+                ++i;
+            } else {
+                if (j + 1 >= H.size()) { total += 1 + (int64_t)(L.size() - i); break; }
+                ++j;
+                x_add(&r, &H[j]);
+                x_sub(&r, &W);
+            }
+        }
+    }
+    return total;
 }
 
 /* Light buckets one by one (Section 2.2: a light item keeps its whole weight in
