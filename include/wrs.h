@@ -53,10 +53,14 @@ enum {
     WRS_ENOTFOUND = -6  /* server: unknown table or request id */
 };
 
-enum { WRS_OP_BUILD = 1, WRS_OP_WOR = 2 };
+enum { WRS_OP_BUILD = 1, WRS_OP_WOR = 2, WRS_OP_BUILD_PLUS = 3 };
+
+/* Items per greedy block of wrs_alias_build_plus (part of its result). */
+#define WRS_PSAPLUS_BLOCK 2048
 
 /* Bytes of device workspace needed by wrs_alias_build (op = WRS_OP_BUILD, k
- * ignored) or wrs_sample_wor (op = WRS_OP_WOR).  Depends on n (and k) only.
+ * ignored), wrs_alias_build_plus (op = WRS_OP_BUILD_PLUS, k ignored) or
+ * wrs_sample_wor (op = WRS_OP_WOR).  Depends on n (and k) only.
  * Returns 0 for invalid arguments. */
 size_t wrs_workspace_bytes(int op, int64_t n, int64_t k);
 
@@ -72,6 +76,24 @@ size_t wrs_workspace_bytes(int op, int64_t n, int64_t k);
  * and the total weight (wrs_total_weight). */
 int wrs_alias_build(const float* d_w, int64_t n, wrs_entry* d_table,
                     void* d_ws, size_t ws_bytes, void* stream);
+
+/* Build an alias table with greedy blocks first (Section 4.2.1, PSA+).  The
+ * items are cut into consecutive blocks of WRS_PSAPLUS_BLOCK items; inside
+ * each block the sweep of Section 4.1 runs on the block's own items until the
+ * block runs out of light or of heavy items, and what it packed is final.
+ * The items left (the heavy each block stopped at, with the part of its size
+ * not yet placed, and the untouched items) then go through the splitting
+ * construction of wrs_alias_build, in index order.  The table differs from
+ * wrs_alias_build's; it is the sequential definition of this two-stage
+ * construction in the same exact grid arithmetic.
+ * Arguments as for wrs_alias_build, with d_ws of
+ * wrs_workspace_bytes(WRS_OP_BUILD_PLUS, n, 0) bytes.  The call blocks the
+ * calling thread until the greedy stage has run on the stream (it sizes the
+ * second stage from the number of items left), so it cannot be captured in a
+ * graph; the second stage is queued on the stream when the call returns.
+ * Device-side errors (weight domain) are reported through wrs_status. */
+int wrs_alias_build_plus(const float* d_w, int64_t n, wrs_entry* d_table,
+                         void* d_ws, size_t ws_bytes, void* stream);
 
 /* Draw k samples with replacement from a table: d_out[s] = query at counter
  * c = first_counter + s, for s in [0, k).  One Philox block per draw with

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwrs.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EDEVICE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-OP_BUILD, OP_WOR = 1, 2
+OP_BUILD, OP_WOR, OP_BUILD_PLUS = 1, 2, 3
+PSAPLUS_BLOCK = 2048  # items per greedy block of alias_build_plus
 TUNE_BUILD, TUNE_SAMPLE = 1, 2
 
 _lib = None
@@ -52,6 +53,8 @@ EXPORTS = {
     "wrs_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64]),
     "wrs_alias_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p]),
+    "wrs_alias_build_plus": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_size_t, ctypes.c_void_p]),
     "wrs_alias_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
                                         ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "wrs_sample_wor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
@@ -160,6 +163,12 @@ def workspace_bytes(op: int, n: int, k: int = 0) -> int:
 
 def alias_build(w, n, table, ws, stream=None):
     _check("wrs_alias_build", lib().wrs_alias_build(_ptr(w), n, _ptr(table), _ptr(ws), ws.numel() if hasattr(ws, "numel") else ws_bytes_of(ws), _stream(stream)))
+
+
+def alias_build_plus(w, n, table, ws, stream=None):
+    """Greedy blocks, then the splitting construction on the items left
+    (blocks the calling thread until the greedy stage has run)."""
+    _check("wrs_alias_build_plus", lib().wrs_alias_build_plus(_ptr(w), n, _ptr(table), _ptr(ws), ws.numel() if hasattr(ws, "numel") else ws_bytes_of(ws), _stream(stream)))
 
 
 def ws_bytes_of(ws):

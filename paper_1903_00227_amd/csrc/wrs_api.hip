@@ -37,6 +37,7 @@ extern "C" const char* wrs_last_error(void) { return g_err; }
 extern "C" size_t wrs_workspace_bytes(int op, int64_t n, int64_t k) {
     if (n < 1 || n > N_MAX || k < 0) return 0;
     if (op == WRS_OP_BUILD) return build_ws_bytes(n);
+    if (op == WRS_OP_BUILD_PLUS) return plus_ws_bytes(n);
     if (op == WRS_OP_WOR) return wor_ws_bytes(n, k);
     return 0;
 }
@@ -59,6 +60,53 @@ extern "C" int wrs_alias_build(const float* d_w, int64_t n, wrs_entry* d_table, 
     phase_blocks(J, blocks);
     hipError_t e = launch_build(jt, blocks, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail("wrs_alias_build launch", e);
+    return WRS_OK;
+}
+
+extern "C" int wrs_alias_build_plus(const float* d_w, int64_t n, wrs_entry* d_table, void* d_ws, size_t ws_bytes,
+                                    void* stream) {
+    g_err[0] = 0;
+    if (!d_w || !d_table || !d_ws) { set_error("wrs_alias_build_plus: null pointer"); return WRS_EINVAL; }
+    if (n < 1 || n > N_MAX) { set_error("wrs_alias_build_plus: n = %lld out of [1, 2^31-1]", (long long)n); return WRS_EINVAL; }
+    if (ws_bytes < plus_ws_bytes(n)) { set_error("wrs_alias_build_plus: workspace %zu < %zu bytes", ws_bytes, plus_ws_bytes(n)); return WRS_EINVAL; }
+    if (((uintptr_t)d_ws) & 255) { set_error("wrs_alias_build_plus: workspace not 256-byte aligned"); return WRS_EINVAL; }
+    if (((uintptr_t)d_table) & 7) { set_error("wrs_alias_build_plus: table not 8-byte aligned"); return WRS_EINVAL; }
+    const hipStream_t st = (hipStream_t)stream;
+    // stage 0: total weight and grid (the reduction phases only)
+    JobTable jt;
+    memset(&jt, 0, sizeof jt);
+    JobDesc& J = jt.one;
+    J.w = d_w;
+    J.table = d_table;
+    build_ws_layout(J, d_ws, n);
+    int64_t blocks[PH_COUNT];
+    phase_blocks(J, blocks);
+    for (int p = PH_TILE; p < PH_COUNT; ++p) blocks[p] = 0;
+    hipError_t e = launch_build(jt, blocks, st);
+    if (e != hipSuccess) return dev_fail("wrs_alias_build_plus launch", e);
+    // stage 1: greedy blocks, their leftovers compacted into a list
+    const PlusLayout P = plus_layout(d_ws, n);
+    e = launch_greedy(J, P, st);
+    if (e != hipSuccess) return dev_fail("wrs_alias_build_plus greedy launch", e);
+    BuildScalars h;
+    e = hipMemcpyAsync(&h, J.sc, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return dev_fail("wrs_alias_build_plus leftover count", e);
+    if (h.status != WRS_OK || h.nleft <= 0) return WRS_OK;  // status stays in the workspace
+    if (h.nleft > n) { set_error("wrs_alias_build_plus: leftover count %lld > n", (long long)h.nleft); return WRS_EDEVICE; }
+    // stage 2: the splitting construction over the list
+    JobTable jl;
+    memset(&jl, 0, sizeof jl);
+    JobDesc& L = jl.one;
+    L = J;
+    L.w = P.lw;
+    L.lidx = P.lidx;
+    L.lres = P.res;
+    L.PI = P.PI;
+    build_list_layout(L, h.nleft);
+    phase_blocks(L, blocks);
+    e = launch_build(jl, blocks, st, true);
+    if (e != hipSuccess) return dev_fail("wrs_alias_build_plus list launch", e);
     return WRS_OK;
 }
 

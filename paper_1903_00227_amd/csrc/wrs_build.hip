@@ -35,7 +35,6 @@
 
 namespace wrs {
 
-static constexpr int32_t FH_NONE = 0x7fffffff;
 
 // ---------------------------------------------------------------------------
 // Workspace layout of one table.
@@ -101,6 +100,58 @@ void build_ws_layout(JobDesc& J, void* ws, int64_t n, int32_t psteps) {
     J.sDP = (u128*)(b + L.sDP);
     J.sEP = (u128*)(b + L.sEP);
     J.sFH = (int32_t*)(b + L.sFH);
+    J.lidx = nullptr;
+    J.lres = nullptr;
+    J.PI = nullptr;
+    J.nmul = (uint32_t)n;
+}
+
+void build_list_layout(JobDesc& J, int64_t m) {
+    J.n = m;
+    J.ntiles = (int32_t)cdiv(m, TILE);
+    J.nred = 0;
+    J.nseg = (int32_t)cdiv(J.ntiles, SCAN_SEG);
+    J.psteps = pack_steps_for(m);
+    J.npack = (int32_t)pack_blocks(J.ntiles, J.psteps);
+}
+
+// PSA+ workspace: the build workspace of n items, then the greedy arrays.
+struct PlusOffsets {
+    size_t cnt, goff, res, sidx, sw, lidx, lw, PI, total;
+};
+
+static PlusOffsets plus_offsets(int64_t n) {
+    const int64_t G = cdiv(n, GTILE);
+    const int64_t C = cdiv(n, TILE);
+    PlusOffsets P;
+    size_t o = layout_for(n).total;
+    P.cnt = o;  o = align256(o + sizeof(uint32_t) * G);
+    P.goff = o; o = align256(o + sizeof(uint32_t) * G);
+    P.res = o;  o = align256(o + sizeof(u128) * G);
+    P.sidx = o; o = align256(o + sizeof(uint32_t) * G * GTILE);
+    P.sw = o;   o = align256(o + sizeof(float) * G * GTILE);
+    P.lidx = o; o = align256(o + sizeof(uint32_t) * C * TILE);
+    P.lw = o;   o = align256(o + sizeof(float) * C * TILE);
+    P.PI = o;   o = align256(o + sizeof(uint32_t) * C * TILE);
+    P.total = o;
+    return P;
+}
+
+size_t plus_ws_bytes(int64_t n) { return plus_offsets(n).total; }
+
+PlusLayout plus_layout(void* ws, int64_t n) {
+    const PlusOffsets o = plus_offsets(n);
+    char* b = (char*)ws;
+    PlusLayout P;
+    P.cnt = (uint32_t*)(b + o.cnt);
+    P.goff = (uint32_t*)(b + o.goff);
+    P.res = (u128*)(b + o.res);
+    P.sidx = (uint32_t*)(b + o.sidx);
+    P.sw = (float*)(b + o.sw);
+    P.lidx = (uint32_t*)(b + o.lidx);
+    P.lw = (float*)(b + o.lw);
+    P.PI = (uint32_t*)(b + o.PI);
+    return P;
 }
 
 // ---------------------------------------------------------------------------
@@ -210,7 +261,7 @@ __device__ void finalize_scalars(const JobDesc& J, double hi, double lo, uint32_
     S.wthr = 0;
     S.tscale = 0;
     S.Qk = 0;
-    S.pad3 = 0;
+    S.nleft = 0;
     if (bad || !(hi > 0.0)) {
         S.status = WRS_EDOMAIN;
     } else {
@@ -283,14 +334,17 @@ __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {
 // that the merge stages one side of a tile without classifying it again.
 constexpr int AGG_VEC = TILE / 256;  // float4 loads per lane
 
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
 
+// List mode (LIST = true, the splitting stage of the greedy construction):
+// the items are a list of original items in index order; a residual marker
+// stands for the exact n-scaled size lres[slot] (light iff it is at most Q),
+// FH holds original indices, and the partitioned copy carries original
+// indices (PI) instead of tile offsets.
+template <bool LIST>
 __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
     __shared__ int s_job;
     __shared__ float s_w[TILES_PER_AGG_BLOCK][TILE];
-    __shared__ uint16_t s_o[TILES_PER_AGG_BLOCK][TILE];
+    __shared__ uint32_t s_o[TILES_PER_AGG_BLOCK][LIST ? TILE : TILE / 2];  // u16 offsets, or u32 indices
     int64_t lb;
     const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
     const BuildScalars* sc = J.sc;
@@ -303,16 +357,28 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
     const uint32_t wthr = uni(sc->wthr);
     const u128 Q = uni(sc->Q);
     const int64_t n = J.n;
+    const uint32_t nmul = J.nmul;
     const int64_t base = c * TILE;
+    uint16_t* s_o16 = (uint16_t*)&s_o[wv][0];
     if (active) {
         const int cnt = (int)min((int64_t)TILE, n - base);
         const WRS_GLOBAL float* w = glb(J.w) + base;
         const bool vec = (cnt == TILE) && ((((uintptr_t)w) & 15) == 0);
         float v[4 * AGG_VEC];
+        uint32_t oid[LIST ? 4 * AGG_VEC : 1];
         if (vec) {  // all loads in flight together
             vfloat4 x[AGG_VEC];
 #pragma unroll
             for (int r = 0; r < AGG_VEC; ++r) x[r] = *(const WRS_GLOBAL vfloat4*)(w + r * 256 + lane * 4);
+            if constexpr (LIST) {
+                vuint4 y[AGG_VEC];
+#pragma unroll
+                for (int r = 0; r < AGG_VEC; ++r) y[r] = *(const WRS_GLOBAL vuint4*)(glb(J.lidx) + base + r * 256 + lane * 4);
+#pragma unroll
+                for (int r = 0; r < AGG_VEC; ++r) {
+                    oid[4 * r] = y[r].x; oid[4 * r + 1] = y[r].y; oid[4 * r + 2] = y[r].z; oid[4 * r + 3] = y[r].w;
+                }
+            }
 #pragma unroll
             for (int r = 0; r < AGG_VEC; ++r) {
                 v[4 * r] = x[r].x; v[4 * r + 1] = x[r].y; v[4 * r + 2] = x[r].z; v[4 * r + 3] = x[r].w;
@@ -324,20 +390,56 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
                 for (int e = 0; e < 4; ++e) {
                     const int i = r * 256 + lane * 4 + e;
                     v[4 * r + e] = (i < cnt) ? w[i] : 0.0f;
+                    if constexpr (LIST) oid[4 * r + e] = (i < cnt) ? glb(J.lidx)[base + i] : 0u;
                 }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4 * AGG_VEC; ++k) v[k] = canonical_weight(v[k]);
+        // List mode: residual markers (rare) carry exact sizes; their q is 0
+        // in the sums below and their sizes are added separately.
+        uint32_t lmask = 0;  // LIST: bit k = item k is light
+        u128 mres_l = 0, mres_h = 0;
+        if constexpr (LIST) {
+            bool anym = false;
+#pragma unroll
+            for (int k = 0; k < 4 * AGG_VEC; ++k) anym |= is_residual_marker(__float_as_uint(v[k]));
+#pragma unroll
+            for (int k = 0; k < 4 * AGG_VEC; ++k) {
+                const int i = (k >> 2) * 256 + lane * 4 + (k & 3);
+                lmask |= (uint32_t)((i < cnt) && (__float_as_uint(v[k]) < wthr)) << k;
+            }
+            if (__ballot(anym) != 0) {
+                for (int k = 0; k < 4 * AGG_VEC; ++k) {
+                    const uint32_t bits = __float_as_uint(v[k]);
+                    if (is_residual_marker(bits)) {
+                        const u128 m = glb(J.lres)[residual_slot(bits)];
+                        const bool light = m <= Q;
+                        lmask |= (uint32_t)light << k;
+                        if (light) mres_l += m; else mres_h += m;
+                    }
+                }
+                mres_l = lane63(wave_incl_scan(mres_l));
+                mres_h = lane63(wave_incl_scan(mres_h));
             }
         }
         // light flags, as one ballot per (load, element)
         // (items past the tile's end hold 0, which adds nothing)
         auto is_light = [&](int r, int e) -> bool {
+            if constexpr (LIST) return (lmask >> (4 * r + e)) & 1u;
             return (r * 256 + lane * 4 + e < cnt) && (__float_as_uint(v[4 * r + e]) < wthr);
+        };
+        // the weight whose q enters the sums (a marker's size is added apart)
+        auto qw = [&](int k) -> float {
+            if constexpr (LIST) return is_residual_marker(__float_as_uint(v[k])) ? 0.0f : v[k];
+            return v[k];
         };
         uint32_t nl = 0;
         u128 sq = 0, sql = 0;
         int fh = FH_NONE;
         int smin = 0;
 #pragma unroll
-        for (int k = 0; k < 4 * AGG_VEC; ++k) smin = min(smin, grid_shift(v[k], G));
+        for (int k = 0; k < 4 * AGG_VEC; ++k) smin = min(smin, grid_shift(qw(k), G));
         if (__ballot(smin < 0) == 0) {
             // every weight of the tile lies on the grid
 #pragma unroll
@@ -345,7 +447,7 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const bool light = is_light(r, e);
-                    const u128 q = quantize_on_grid(v[4 * r + e], G);
+                    const u128 q = quantize_on_grid(qw(4 * r + e), G);
                     sq += q;
                     sql += light ? q : (u128)0;
                 }
@@ -353,7 +455,7 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
         } else {
             for (int k = 0; k < 4 * AGG_VEC; ++k) {
                 const bool light = is_light(k >> 2, k & 3);
-                const u128 q = quantize(v[k], G);
+                const u128 q = quantize(qw(k), G);
                 sq += q;
                 sql += light ? q : (u128)0;
             }
@@ -383,7 +485,7 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
                 const int p = light ? (int)lr : (int)(nl + (uint32_t)i - lr);
                 if (i < cnt) {
                     s_w[wv][p] = v[4 * r + e];
-                    s_o[wv][p] = (uint16_t)i;
+                    if constexpr (LIST) s_o[wv][p] = oid[4 * r + e]; else s_o16[p] = (uint16_t)i;
                 }
                 lr += light;
             }
@@ -395,8 +497,9 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
         if (lane == 0) {
             const uint32_t nh = (uint32_t)cnt - nl;
             glb(J.NL)[c] = nl;
-            glb(J.DP)[c] = (u128)nl * Q - (u128)n * sql;
-            glb(J.EP)[c] = (u128)n * sqh - (u128)nh * Q;
+            glb(J.DP)[c] = (u128)nl * Q - (u128)nmul * sql - mres_l;
+            glb(J.EP)[c] = (u128)nmul * sqh + mres_h - (u128)nh * Q;
+            if constexpr (LIST) fh = (fh == FH_NONE) ? FH_NONE : (int)glb(J.lidx)[fh];
             glb(J.FH)[c] = fh;
         }
     }
@@ -405,17 +508,22 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
         // whole tile (the arrays are padded to whole tiles); entries past the
         // tile's item count are never read
         WRS_GLOBAL float* wp = glb(J.WP) + base;
-        WRS_GLOBAL uint16_t* po = glb(J.PO) + base;
 #pragma unroll
         for (int r = 0; r < AGG_VEC; ++r) {
             const int i0 = r * 256 + lane * 4;
             vfloat4 x;
             x.x = s_w[wv][i0]; x.y = s_w[wv][i0 + 1]; x.z = s_w[wv][i0 + 2]; x.w = s_w[wv][i0 + 3];
             *(WRS_GLOBAL vfloat4*)(wp + i0) = x;
-            vuint2 o;
-            o.x = (uint32_t)s_o[wv][i0] | ((uint32_t)s_o[wv][i0 + 1] << 16);
-            o.y = (uint32_t)s_o[wv][i0 + 2] | ((uint32_t)s_o[wv][i0 + 3] << 16);
-            *(WRS_GLOBAL vuint2*)(po + i0) = o;
+            if constexpr (LIST) {
+                vuint4 o;
+                o.x = s_o[wv][i0]; o.y = s_o[wv][i0 + 1]; o.z = s_o[wv][i0 + 2]; o.w = s_o[wv][i0 + 3];
+                *(WRS_GLOBAL vuint4*)(glb(J.PI) + base + i0) = o;
+            } else {
+                vuint2 o;
+                o.x = (uint32_t)s_o16[i0] | ((uint32_t)s_o16[i0 + 1] << 16);
+                o.y = (uint32_t)s_o16[i0 + 2] | ((uint32_t)s_o16[i0 + 3] << 16);
+                *(WRS_GLOBAL vuint2*)(glb(J.PO) + base + i0) = o;
+            }
         }
     }
 }
@@ -673,21 +781,28 @@ __global__ __launch_bounds__(TPB) void k_split(JobTable jt) {
 // The two sides of the merge staged in LDS: the lights of tile x with the
 // deficit sum before each as key, and the heavies of tile y with the excess
 // sum through each.  Both come in index order from the partitioned copy of
-// the tile that k_tileagg wrote.
+// the tile that k_tileagg wrote.  An item is named by its offset inside the
+// tile, or in list mode by its original index.
+template <bool LIST> struct ItemId { typedef uint16_t type; };
+template <> struct ItemId<true> { typedef uint32_t type; };
+
+template <bool LIST>
 struct LightSlot {
     uint64_t key[TILE];
-    float w[TILE];        // a light's bucket keeps n w / W
-    uint16_t off[TILE];   // item offset inside the tile
+    float t[TILE];        // a light's bucket keeps n w / W (at most 1)
+    typename ItemId<LIST>::type id[TILE];
 };
 
+template <bool LIST>
 struct HeavySlot {
     uint64_t key[TILE];
-    uint16_t off[TILE];
+    typename ItemId<LIST>::type id[TILE];
 };
 
+template <bool LIST>
 struct PackShared {
-    LightSlot A;
-    HeavySlot B;
+    LightSlot<LIST> A;
+    HeavySlot<LIST> B;
     uint64_t tmp[TPB / 64];
     uint64_t dp[PACK_STEPS_MAX + 2];   // DP64[x0 + i]
     uint64_t ep[PACK_STEPS_MAX + 2];   // EP64[y0 + i]
@@ -707,6 +822,7 @@ struct SideFetch {
 };
 
 // side items [first, first + cnt) of the partitioned tile c
+template <bool LIST>
 __device__ __forceinline__ void fetch_side(const JobDesc& J, int64_t c, int first, int cnt, bool light,
                                            SideFetch& f) {
     f.cnt = cnt;
@@ -717,52 +833,50 @@ __device__ __forceinline__ void fetch_side(const JobDesc& J, int64_t c, int firs
     const int j0 = (int)threadIdx.x * k;
     const WRS_GLOBAL float* wp = glb(J.WP) + c * TILE + first;
     const WRS_GLOBAL uint16_t* po = glb(J.PO) + c * TILE + first;
+    const WRS_GLOBAL uint32_t* pi = glb(J.PI) + c * TILE + first;
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         if (e < k) {
             const int j = j0 + e;
             if (j < cnt) {
                 f.v[e] = wp[j];
-                f.o[e] = po[j];
+                if constexpr (LIST) f.o[e] = pi[j]; else f.o[e] = po[j];
             }
         }
     }
 }
 
-// n q(w) / 2^kshift rounded to nearest (ties up): the item's size in key
-// units.  On the grid (s >= 0) n q = (n m) 2^s exactly; below it q is rounded
-// first.  The result is below 2^62 for every weight <= W.
-__device__ __forceinline__ uint64_t size_keyunits(float w, const BuildScalars& sc, uint32_t n) {
-    const uint32_t bits = __float_as_uint(w);
-    const uint32_t e = bits >> 23;
-    const uint32_t m = (bits & 0x7FFFFFu) | (e ? 0x800000u : 0u);
-    const int s = (int)max(e, 1u) - 150 - sc.G;
-    uint64_t x = (uint64_t)m * n;  // < 2^55
-    int r = sc.kshift - s;         // right shift
-    if (s < 0) {
-        x = (uint64_t)quantize(w, sc.G) * n;
-        r = sc.kshift;
-    }
-    const uint64_t down = (x + (1ull << ((r - 1) & 63))) >> (r & 63);  // r in [1, 63]: no overflow
-    const uint64_t up = x << (r <= 0 ? min(-r, 63) : 0);
-    return r <= 0 ? up : (r >= 64 ? 0ull : down);
-}
 
 // Stage one side of a tile: keys are the tile's exact prefix plus the rounded
 // sizes of the side's items before (lights) or through (heavies) each item.
-template <bool LIGHT>
-__device__ __forceinline__ void fill_side(uint64_t* key, float* wl, uint16_t* off, const SideFetch& f,
-                                          const BuildScalars& sc, uint32_t n, uint64_t* tmp) {
+// A light's t is computed here too.  List mode: a residual marker's size is
+// its exact n-scaled size from lres, rounded to key units.
+template <bool LIGHT, bool LIST, class Id>
+__device__ __forceinline__ void fill_side(uint64_t* key, float* tl, Id* id, const SideFetch& f,
+                                          const BuildScalars& sc, uint32_t n, double lscale,
+                                          const u128* lres, uint64_t* tmp) {
     const int k = (f.cnt + TPB - 1) / TPB;
     const int j0 = (int)threadIdx.x * k;
     const uint64_t Qk = sc.Qk;
     uint64_t inc[IPT];
+    float tv[LIGHT ? IPT : 1];
     uint64_t sum = 0;
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         inc[e] = 0;
         if (e < k && j0 + e < f.cnt) {
-            const uint64_t z = size_keyunits(f.v[e], sc, n);
+            uint64_t z;
+            float t = 0.0f;
+            if (LIST && is_residual_marker(__float_as_uint(f.v[e]))) {
+                const u128 m = glb(lres)[residual_slot(__float_as_uint(f.v[e]))];
+                const int ks = sc.kshift;
+                z = (uint64_t)(ks > 0 ? (m + ((u128)1 << (ks - 1))) >> ks : m);
+                if (LIGHT) t = (float)(u128_to_double(m) * sc.rQ);
+            } else {
+                z = size_keyunits(f.v[e], sc, n);
+                if (LIGHT) t = light_t(f.v[e], lscale);
+            }
+            if constexpr (LIGHT) tv[e] = fminf(t, 1.0f);
             inc[e] = LIGHT ? Qk - z : z - Qk;
             sum += inc[e];
         }
@@ -780,68 +894,35 @@ __device__ __forceinline__ void fill_side(uint64_t* key, float* wl, uint16_t* of
         if (e < k) {
             const int j = j0 + e;
             if (j < f.cnt) {
-                if (LIGHT) {
+                if constexpr (LIGHT) {
                     key[j] = acc;
-                    wl[j] = f.v[e];
+                    tl[j] = tv[e];
                     acc += inc[e];
                 } else {
                     acc += inc[e];
                     key[j] = acc;
                 }
-                off[j] = (uint16_t)f.o[e];
+                id[j] = (Id)f.o[e];
             }
         }
     }
     __syncthreads();
 }
 
-// First position p in [from, to) with !(key[p] < v) (keys non-decreasing): a
-// 64-ary search by one wave, two rounds for a tile.
-template <bool LE>
-__device__ __forceinline__ int wave_search(const uint64_t* key, int from, int to, uint64_t v) {
-    const int lane = threadIdx.x & 63;
-    int lo = from, hi = to;  // answer in [lo, hi]
-    while (lo < hi) {
-        const int step = (hi - lo + 63) >> 6;
-        const int p = lo + lane * step;
-        const bool pr = (p < hi) && (LE ? (key[p] <= v) : (key[p] < v));
-        const uint64_t mask = __ballot(pr);
-        const int K = __popcll(mask);
-        if (K == 0) {
-            hi = lo;
-        } else {
-            const int pk1 = lo + (K - 1) * step;
-            const int nhi = min(hi, pk1 + step);
-            lo = pk1 + 1;
-            hi = nhi;
-        }
-    }
-    return lo;
-}
 
-__device__ __forceinline__ void store_entry(wrs_entry* table, int64_t item, float t, int32_t alias) {
-    vuint2 v;
-    v.x = __float_as_uint(t);
-    v.y = (uint32_t)alias;
-    *(WRS_GLOBAL vuint2*)(table + item) = v;
-}
 
-// A light's bucket keeps t = n w / W; lscale = n 2^-G / Q.
-__device__ __forceinline__ float light_t(float w, double lscale) { return (float)((double)w * lscale); }
 
-// A heavy's bucket keeps t = 1 + (E - D) / W, from a key difference.
-__device__ __forceinline__ float heavy_t(uint64_t E, uint64_t D, double tscale) {
-    const float t = (float)fma((double)(int64_t)(E - D), tscale, 1.0);
-    return fminf(fmaxf(t, 0.0f), 1.0f);
-}
 
+template <bool LIST>
 __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
-    __shared__ PackShared sh;
+    __shared__ PackShared<LIST> sh;
     int64_t lb;
     const JobDesc J = job_uniform(job_of_block(jt, lb, &sh.s_job, xcd_contiguous_block()));
     if (J.sc->status != WRS_OK) return;
     const BuildScalars sc = scalars_uniform(J.sc);
-    const uint32_t n32 = (uint32_t)J.n;
+    const uint32_t n32 = J.nmul;
+    const double lscale = sc.nscale * sc.rQ;
+    const u128* lres = J.lres;
     const int64_t C = J.ntiles;
     const int psteps = J.psteps;  // PACK_STEPS_MIN..PACK_STEPS_MAX
     const int64_t s0 = lb * psteps;
@@ -868,12 +949,12 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
     SideFetch fa, fb;
     {
         const int la = lights_of(x0);
-        fetch_side(J, x0, 0, la, true, fa);
+        fetch_side<LIST>(J, x0, 0, la, true, fa);
         const int hb = heavies_of(y0);
-        fetch_side(J, y0, y0 < C ? tile_cnt(y0) - hb : 0, hb, false, fb);
+        fetch_side<LIST>(J, y0, y0 < C ? tile_cnt(y0) - hb : 0, hb, false, fb);
     }
-    fill_side<true>(sh.A.key, sh.A.w, sh.A.off, fa, sc, n32, sh.tmp);
-    fill_side<false>(sh.B.key, nullptr, sh.B.off, fb, sc, n32, sh.tmp);
+    fill_side<true, LIST>(sh.A.key, sh.A.t, sh.A.id, fa, sc, n32, lscale, lres, sh.tmp);
+    fill_side<false, LIST>(sh.B.key, (float*)nullptr, sh.B.id, fb, sc, n32, lscale, lres, sh.tmp);
     int nlx = fa.cnt, nhy = fb.cnt;
     int64_t x = x0, y = y0;
     // DPkey(x) < v, with DPkey(C) = +infinity
@@ -888,9 +969,10 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
         }
     }
     const double tscale = sc.tscale;
-    const double lscale = sc.nscale * sc.rQ;
-    const LightSlot& A = sh.A;
-    const HeavySlot& B = sh.B;
+    const LightSlot<LIST>& A = sh.A;
+    const HeavySlot<LIST>& B = sh.B;
+    // original item of a staged entry: tile base + offset, or the list's index
+    auto item = [&](int64_t tbase, uint32_t id) -> int64_t { return LIST ? (int64_t)id : tbase + id; };
     for (int64_t s = s0; s < s1; ++s) {
         const int xi = (int)(x - x0), yi = (int)(y - y0);
         const bool has_h = y + 1 <= C;
@@ -903,9 +985,9 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
         if (need) {
             if (heavy_ev) {
                 const int hc = heavies_of(y + 1);
-                fetch_side(J, y + 1, y + 1 < C ? tile_cnt(y + 1) - hc : 0, hc, false, fn);
+                fetch_side<LIST>(J, y + 1, y + 1 < C ? tile_cnt(y + 1) - hc : 0, hc, false, fn);
             } else {
-                fetch_side(J, x + 1, 0, lights_of(x + 1), true, fn);
+                fetch_side<LIST>(J, x + 1, 0, lights_of(x + 1), true, fn);
             }
         }
         const int64_t abase = x * TILE, bbase = y * TILE;
@@ -923,11 +1005,11 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
         if (nhc == 0 && nlc > 0) {
             // lights only: all take the same alias; lanes take consecutive lights
             const bool hv = ph < nhy;
-            const int32_t al = hv ? (int32_t)(bbase + B.off[ph]) : nextH;
+            const int32_t al = hv ? (int32_t)item(bbase, B.id[ph]) : nextH;
             for (int d = threadIdx.x; d < nlc; d += TPB) {
                 const int lp = pl + d;
-                const int64_t own = abase + A.off[lp];
-                const float t = fminf(light_t(A.w[lp], lscale), 1.0f);
+                const int64_t own = item(abase, A.id[lp]);
+                const float t = A.t[lp];
                 const int32_t a2 = (!hv && al == FH_NONE) ? (int32_t)own : al;
                 store_entry(J.table, own, t, a2);
             }
@@ -937,8 +1019,8 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
             for (int d = threadIdx.x; d < nhc; d += TPB) {
                 const int hp = ph + d;
                 const float t = heavy_t(B.key[hp], Dn, tscale);
-                const int64_t own = bbase + B.off[hp];
-                const int32_t al = (hp + 1 < nhy) ? (int32_t)(bbase + B.off[hp + 1])
+                const int64_t own = item(bbase, B.id[hp]);
+                const int32_t al = (hp + 1 < nhy) ? (int32_t)item(bbase, B.id[hp + 1])
                                                   : (nextH != FH_NONE ? nextH : (int32_t)own);
                 store_entry(J.table, own, t, al);
             }
@@ -966,11 +1048,11 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                 for (int d = d0; d < d1; ++d) {
                     const bool take_h = (j < nhc) && (i >= nlc || kb <= ka);
                     const int ia = min(pl + i, TILE - 1), ib = min(ph + j, TILE - 1);
-                    const int64_t own = take_h ? bbase + B.off[ib] : abase + A.off[ia];
+                    const int64_t own = take_h ? item(bbase, B.id[ib]) : item(abase, A.id[ia]);
                     const int q = ph + j + (take_h ? 1 : 0);
-                    const int32_t al = (q < nhy) ? (int32_t)(bbase + B.off[q])
+                    const int32_t al = (q < nhy) ? (int32_t)item(bbase, B.id[q])
                                                  : (nextH != FH_NONE ? nextH : (int32_t)own);
-                    const float t = take_h ? heavy_t(kb, ka, tscale) : fminf(light_t(A.w[ia], lscale), 1.0f);
+                    const float t = take_h ? heavy_t(kb, ka, tscale) : A.t[ia];
                     store_entry(J.table, own, t, al);
                     if (take_h) {
                         ++j;
@@ -991,14 +1073,14 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
             ++y;
             ph = 0;
             if (need) {
-                fill_side<false>(sh.B.key, nullptr, sh.B.off, fn, sc, n32, sh.tmp);
+                fill_side<false, LIST>(sh.B.key, (float*)nullptr, sh.B.id, fn, sc, n32, lscale, lres, sh.tmp);
                 nhy = fn.cnt;
             }
         } else {
             ++x;
             pl = 0;
             if (need) {
-                fill_side<true>(sh.A.key, sh.A.w, sh.A.off, fn, sc, n32, sh.tmp);
+                fill_side<true, LIST>(sh.A.key, sh.A.t, sh.A.id, fn, sc, n32, lscale, lres, sh.tmp);
                 nlx = fn.cnt;
             }
         }
@@ -1080,7 +1162,7 @@ void phase_blocks(const JobDesc& J, int64_t b[PH_COUNT]) {
     b[PH_SAMPLE] = sample_blocks(J);
 }
 
-hipError_t launch_build(const JobTable& jt0, const int64_t* blocks, hipStream_t st) {
+hipError_t launch_build(const JobTable& jt0, const int64_t* blocks, hipStream_t st, bool list) {
     JobTable jt = jt0;
 #define WRS_LAUNCH(kern, ph)                                                       \
     do {                                                                           \
@@ -1093,12 +1175,12 @@ hipError_t launch_build(const JobTable& jt0, const int64_t* blocks, hipStream_t 
     } while (0)
     WRS_LAUNCH(k_reduce, PH_RED);
     WRS_LAUNCH(k_finalize, PH_FIN);
-    WRS_LAUNCH(k_tileagg, PH_TILE);
+    if (list) WRS_LAUNCH(k_tileagg<true>, PH_TILE); else WRS_LAUNCH(k_tileagg<false>, PH_TILE);
     WRS_LAUNCH(k_scan_seg, PH_SEG);
     WRS_LAUNCH(k_scan_top, PH_TOP);
     WRS_LAUNCH(k_scan_fix, PH_FIX);
     WRS_LAUNCH(k_split, PH_SPLIT);
-    WRS_LAUNCH(k_pack, PH_PACK);
+    if (list) WRS_LAUNCH(k_pack<true>, PH_PACK); else WRS_LAUNCH(k_pack<false>, PH_PACK);
 #undef WRS_LAUNCH
     return hipSuccess;
 }

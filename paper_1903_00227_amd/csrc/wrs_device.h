@@ -42,6 +42,10 @@ __device__ __forceinline__ u128 quantize(float w, int G) {
     return (u128)(r + ((rem > half) || (rem == half && (r & 1u))));
 }
 
+// A weight with its sign bit cleared: -0 (which the domain check accepts, as
+// -0 >= 0) becomes +0, the only form the bit-pattern arithmetic below expects.
+__device__ __forceinline__ float canonical_weight(float w) { return __uint_as_float(__float_as_uint(w) & 0x7FFFFFFFu); }
+
 // Exponent of w on the grid: w = m 2^s (s < 0: below the grid).
 __device__ __forceinline__ int grid_shift(float w, int G) {
     const uint32_t e = __float_as_uint(w) >> 23;
@@ -257,6 +261,7 @@ __device__ __forceinline__ WRS_GLOBAL T* glb(T* p) {
 // through an address-space-qualified pointer.
 typedef float vfloat4 __attribute__((ext_vector_type(4)));
 typedef uint32_t vuint2 __attribute__((ext_vector_type(2)));
+typedef uint32_t vuint4 __attribute__((ext_vector_type(4)));
 
 // Values that every lane holds alike, moved to scalar registers.  The job
 // descriptor and the build scalars are read once per block this way; left in
@@ -279,7 +284,7 @@ __device__ __forceinline__ T* uni(T* p) {
 
 // Every field is copied: a field added to JobDesc or BuildScalars must be
 // added here too (the size checks catch a forgotten one).
-static_assert(sizeof(JobDesc) == 216, "job_uniform copies every JobDesc field");
+static_assert(sizeof(JobDesc) == 248, "job_uniform copies every JobDesc field");
 static_assert(sizeof(BuildScalars) == 128, "scalars_uniform copies every BuildScalars field");
 
 __device__ __forceinline__ JobDesc job_uniform(const JobDesc& J) {
@@ -314,6 +319,11 @@ __device__ __forceinline__ JobDesc job_uniform(const JobDesc& J) {
     u.sDP = uni(J.sDP);
     u.sEP = uni(J.sEP);
     u.sFH = uni(J.sFH);
+    u.lidx = uni(J.lidx);
+    u.lres = uni(J.lres);
+    u.PI = uni(J.PI);
+    u.nmul = uni(J.nmul);
+    u.pad = 0;
     return u;
 }
 
@@ -334,7 +344,7 @@ __device__ __forceinline__ BuildScalars scalars_uniform(const BuildScalars* p) {
     u.wthr = uni(p->wthr);
     u.tscale = uni(p->tscale);
     u.Qk = uni(p->Qk);
-    u.pad3 = 0;
+    u.nleft = uni(p->nleft);
     return u;
 }
 
@@ -367,6 +377,74 @@ __device__ __forceinline__ const JobDesc& job_of_block(const JobTable& jt, int64
     const int j = *s_job;
     lb = b - off[j];
     return jt.jobs[j];
+}
+
+// ---------------------------------------------------------------------------
+// Merge helpers of the table construction (tile merge and greedy blocks).
+// ---------------------------------------------------------------------------
+static constexpr int32_t FH_NONE = 0x7fffffff;
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// n q(w) / 2^kshift rounded to nearest (ties up): the item's size in key
+// units.  On the grid (s >= 0) n q = (n m) 2^s exactly; below it q is rounded
+// first.  The result is below 2^62 for every weight <= W.
+__device__ __forceinline__ uint64_t size_keyunits(float w, const BuildScalars& sc, uint32_t n) {
+    const uint32_t bits = __float_as_uint(w);
+    const uint32_t e = bits >> 23;
+    const uint32_t m = (bits & 0x7FFFFFu) | (e ? 0x800000u : 0u);
+    const int s = (int)max(e, 1u) - 150 - sc.G;
+    uint64_t x = (uint64_t)m * n;  // < 2^55
+    int r = sc.kshift - s;         // right shift
+    if (s < 0) {
+        x = (uint64_t)quantize(w, sc.G) * n;
+        r = sc.kshift;
+    }
+    const uint64_t down = (x + (1ull << ((r - 1) & 63))) >> (r & 63);  // r in [1, 63]: no overflow
+    const uint64_t up = x << (r <= 0 ? min(-r, 63) : 0);
+    return r <= 0 ? up : (r >= 64 ? 0ull : down);
+}
+
+// First position p in [from, to) with !(key[p] < v) (keys non-decreasing): a
+// 64-ary search by one wave, two rounds for a tile.
+template <bool LE>
+__device__ __forceinline__ int wave_search(const uint64_t* key, int from, int to, uint64_t v) {
+    const int lane = threadIdx.x & 63;
+    int lo = from, hi = to;  // answer in [lo, hi]
+    while (lo < hi) {
+        const int step = (hi - lo + 63) >> 6;
+        const int p = lo + lane * step;
+        const bool pr = (p < hi) && (LE ? (key[p] <= v) : (key[p] < v));
+        const uint64_t mask = __ballot(pr);
+        const int K = __popcll(mask);
+        if (K == 0) {
+            hi = lo;
+        } else {
+            const int pk1 = lo + (K - 1) * step;
+            const int nhi = min(hi, pk1 + step);
+            lo = pk1 + 1;
+            hi = nhi;
+        }
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void store_entry(wrs_entry* table, int64_t item, float t, int32_t alias) {
+    vuint2 v;
+    v.x = __float_as_uint(t);
+    v.y = (uint32_t)alias;
+    *(WRS_GLOBAL vuint2*)(table + item) = v;
+}
+
+// A light's bucket keeps t = n w / W; lscale = n 2^-G / Q.
+__device__ __forceinline__ float light_t(float w, double lscale) { return (float)((double)w * lscale); }
+
+// A heavy's bucket keeps t = 1 + (E - D) / W, from a key difference.
+__device__ __forceinline__ float heavy_t(uint64_t E, uint64_t D, double tscale) {
+    const float t = (float)fma((double)(int64_t)(E - D), tscale, 1.0);
+    return fminf(fmaxf(t, 0.0f), 1.0f);
 }
 
 }  // namespace wrs

@@ -39,7 +39,7 @@ struct alignas(16) BuildScalars {
     uint32_t wthr;    // bit pattern of the smallest heavy FP32 weight
     double tscale;    // 2^kshift / Q: key difference -> bucket fraction
     uint64_t Qk;      // Q >> kshift, rounded to nearest: bucket capacity in key units
-    int64_t pad3;
+    int64_t nleft;    // greedy construction: items its blocks left to the splitting stage
 };
 
 // Everything one table needs on the device.
@@ -74,6 +74,16 @@ struct JobDesc {
     u128* sDP;
     u128* sEP;
     int32_t* sFH;
+    // List mode (the splitting stage of the greedy construction): item p of
+    // the job is original item lidx[p], w[p] is its weight, or a residual
+    // marker (a NaN whose payload indexes lres, the exact n-scaled size of the
+    // part of a heavy not yet placed).  Sizes are always n-scaled by nmul, the
+    // original item count.
+    const uint32_t* lidx;
+    const u128* lres;
+    uint32_t* PI;         // [C * TILE] list mode: original index of each WP item
+    uint32_t nmul;        // n of the size scaling (= n outside list mode)
+    int32_t pad;
 };
 
 enum Phase { PH_RED = 0, PH_FIN, PH_TILE, PH_SEG, PH_TOP, PH_FIX, PH_SPLIT, PH_PACK, PH_SAMPLE, PH_COUNT };
@@ -89,10 +99,40 @@ struct JobTable {
     JobDesc one;
 };
 
+// Greedy blocks of the PSA+ construction: items per block, threads per block.
+constexpr int GTILE = 2048;
+constexpr int GTPB = 256;
+constexpr int GIPT = GTILE / GTPB;
+static_assert(GTILE == WRS_PSAPLUS_BLOCK, "greedy block size is part of the ABI");
+
+// Residual marker: a NaN whose low 23 bits hold 1 + the greedy block.  Weights
+// reach the kernels that test for it with the sign bit cleared (a valid weight
+// is at most 0x7F7FFFFF), so no weight is taken for a marker.
+__host__ __device__ inline uint32_t residual_marker(uint32_t g) { return 0x7F800000u | (g + 1u); }
+__host__ __device__ inline bool is_residual_marker(uint32_t bits) { return bits > 0x7F800000u; }
+__host__ __device__ inline uint32_t residual_slot(uint32_t bits) { return (bits & 0x7FFFFFu) - 1u; }
+
 // Byte size of the per-table workspace and the pointer layout inside it.
 size_t build_ws_bytes(int64_t n);
 // psteps <= 0: the tuned (or default) value for n on the current device
 void build_ws_layout(JobDesc& J, void* ws, int64_t n, int32_t psteps = 0);
+// The same workspace reused by a list-mode job of m <= n items (tile arrays,
+// scan arrays and pack starts are sized for n); counts and pack steps for m.
+void build_list_layout(JobDesc& J, int64_t m);
+// PSA+ workspace: the build workspace of n items, then the greedy stage's
+// arrays; pointers into it.
+struct PlusLayout {
+    uint32_t* cnt;    // [G] items each greedy block left
+    uint32_t* goff;   // [G] exclusive prefix of cnt
+    u128* res;        // [G] exact n-scaled size of each block's residual item
+    uint32_t* sidx;   // [G * GTILE] left items of block g at g * GTILE (index)
+    float* sw;        // [G * GTILE] ... (weight or residual marker)
+    uint32_t* lidx;   // [n] left items, compacted in index order
+    float* lw;        // [n]
+    uint32_t* PI;     // [C * TILE] list-mode partitioned original indices
+};
+size_t plus_ws_bytes(int64_t n);
+PlusLayout plus_layout(void* ws, int64_t n);
 void set_sample_job(JobDesc& J, int64_t k, int32_t sunroll = 0);
 int64_t sample_blocks(const JobDesc& J);
 
@@ -107,7 +147,11 @@ uint64_t tuning_generation();
 void phase_blocks(const JobDesc& J, int64_t blocks[PH_COUNT]);
 
 // Host launchers (stream-ordered).
-hipError_t launch_build(const JobTable& jt, const int64_t* blocks, hipStream_t st);
+// list = true: the list-mode kernels (splitting stage of the greedy construction)
+hipError_t launch_build(const JobTable& jt, const int64_t* blocks, hipStream_t st, bool list = false);
+// Greedy stage of PSA+ for one job (reduction already launched): greedy blocks,
+// prefix of their leftover counts (into sc->nleft), compaction.
+hipError_t launch_greedy(const JobDesc& J, const PlusLayout& P, hipStream_t st);
 hipError_t launch_sample(const JobTable& jt, int64_t blocks, hipStream_t st);
 // jt.jobs[j].sc->status -> d_dst[j] for every job (device memory, jobs on the device)
 hipError_t launch_collect_status(const JobTable& jt, int32_t* d_dst, hipStream_t st);

@@ -16,15 +16,16 @@ def torch_dev():
     return torch.device("cuda:0")
 
 
-def gpu_build(wrs, w_np, dev=None):
-    """Build on the GPU through the C ABI; returns (t, alias, status, table tensor, w tensor)."""
+def gpu_build(wrs, w_np, dev=None, plus=False):
+    """Build on the GPU through the C ABI (plus: the greedy-block construction);
+    returns (t, alias, status, table tensor, w tensor, workspace)."""
     import torch
     dev = dev or torch_dev()
     n = w_np.size
     w = torch.from_numpy(np.ascontiguousarray(w_np, np.float32)).to(dev)
     table = wrs.new_table(n, dev)
-    ws = wrs.new_workspace(wrs.OP_BUILD, n, 0, dev)
-    wrs.alias_build(w, n, table, ws)
+    ws = wrs.new_workspace(wrs.OP_BUILD_PLUS if plus else wrs.OP_BUILD, n, 0, dev)
+    (wrs.alias_build_plus if plus else wrs.alias_build)(w, n, table, ws)
     st = wrs.status(ws)
     tab = table.cpu().numpy()
     t = tab[:, 0].copy().view(np.float32)
@@ -62,6 +63,11 @@ def family(name, n, seed):
         return w
     if name == "sorted_power1":
         return (np.arange(1, n + 1, dtype=np.float64) ** -1.0).astype(np.float32)
+    if name == "negzero":
+        # zero weights written as -0.0 (accepted: -0 >= 0), the rest uniform
+        w = workloads.uniform(n, seed)
+        w[rng.random(n) < 0.1] = np.float32(-0.0)
+        return w
     if name == "tiny_heavies":
         # many heavy items barely above the mean, a few very light items
         w = np.full(n, 1.0, np.float32)

@@ -58,3 +58,25 @@ def test_workspace_depends_on_n_only(wrs):
         jobs[i] = wrs.Job(None, n, None, 4 * n, 0, i, None)
     total = L.wrs_batch_workspace_bytes(jobs, 3)
     assert total >= sum(L.wrs_workspace_bytes(wrs.OP_BUILD, n, 0) for n in (10, 5000, 1 << 20))
+
+
+def test_build_plus_host_validation(wrs):
+    L = wrs.lib()
+    n = 10000
+    plain = L.wrs_workspace_bytes(wrs.OP_BUILD, n, 0)
+    plus = L.wrs_workspace_bytes(wrs.OP_BUILD_PLUS, n, 0)
+    # the greedy stage's arrays come after the build workspace: staging and
+    # list (index + weight each), partitioned indices, per-block counts
+    assert plus >= plain + 5 * 4 * n
+    assert L.wrs_workspace_bytes(wrs.OP_BUILD_PLUS, 0, 0) == 0
+    assert L.wrs_workspace_bytes(wrs.OP_BUILD_PLUS, 2 ** 31, 0) == 0
+    assert L.wrs_alias_build_plus(None, n, None, None, 0, None) == wrs.EINVAL
+    assert "null" in wrs.last_error()
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every check below fails on the host
+    assert L.wrs_alias_build_plus(fake, 0, fake, fake, plus, None) == wrs.EINVAL
+    assert L.wrs_alias_build_plus(fake, n, fake, fake, plus - 1, None) == wrs.EINVAL
+    assert "workspace" in wrs.last_error()
+    assert L.wrs_alias_build_plus(fake, n, fake, ctypes.c_void_p((1 << 20) + 8), plus, None) == wrs.EINVAL
+    assert "aligned" in wrs.last_error()
+    assert L.wrs_alias_build_plus(fake, n, ctypes.c_void_p((1 << 20) + 4), fake, plus, None) == wrs.EINVAL
+    assert wrs.PSAPLUS_BLOCK == 2048

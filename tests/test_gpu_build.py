@@ -26,7 +26,7 @@ def wrs():
 
 SIZES = [1, 2, 3, 5, 63, 1000, 1023, 1024, 1025, 2047, 4096, 5000, 3 * 1024 + 17, 40000, 65536, 65536 + 37]
 FAMILIES = ["uniform", "power0.5", "power1", "power2", "ints", "equal", "one", "dominant", "sorted_power1",
-            "tiny_heavies"]
+            "tiny_heavies", "negzero"]
 
 
 def t_tolerance(n, t_ref):

@@ -1,0 +1,124 @@
+"""GPU parity of the greedy-block construction (C ABI wrs_alias_build_plus,
+Section 4.2.1) against the oracle's exact PSA+ with blocks of 2048 items.
+
+Bar: aliases bit-identical to the oracle's table; every item's mass within
+1e-6 relative of n w_i / W; thresholds within the error of the kernels'
+arithmetic:
+  * a light bucket's t = n w / W (or r / W for a heavy left with r <= W by its
+    block) is within 1 ulp of the correctly rounded value;
+  * a heavy bucket's t = 1 + (E - D) / W comes from 64-bit keys: inside a
+    greedy block the keys are sums of item sizes rounded to the key unit
+    u <= 2^(floor(log2 n) - 60) bucket, off by at most GTILE/2 = 1024 units
+    (1025 with the rounding of the block's own key), and in the splitting
+    stage by at most TILE/2 + 1 = 513 units, plus 1 ulp.
+The sizes span one, several and a ragged last greedy block.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import family, gpu_build, say, ulp_diff
+
+pytestmark = pytest.mark.gpu
+
+BLOCK = 2048
+
+
+@pytest.fixture(scope="module")
+def wrs():
+    import paper_1903_00227_amd as w
+    w.lib()
+    assert w.PSAPLUS_BLOCK == BLOCK
+    return w
+
+
+SIZES = [1, 2, 3, 63, 1000, 2047, 2048, 2049, 4096, 5000, 3 * 2048 + 17, 40000, 65536 + 37, 200001]
+FAMILIES = ["uniform", "power0.5", "power1", "power2", "ints", "equal", "one", "dominant", "sorted_power1",
+            "tiny_heavies", "negzero"]
+
+
+def check_against_psaplus(orc, w, t, a):
+    n = w.size
+    t_ref, a_ref = orc.psaplus_build(w, BLOCK)
+    bad = np.nonzero(a != a_ref)[0]
+    assert bad.size == 0, f"{bad.size} alias mismatches, first at {bad[:5]}: gpu {a[bad[:5]]} ref {a_ref[bad[:5]]}"
+    unit = 2.0 ** (int(n).bit_length() - 1 - 60)
+    ulp = np.spacing(np.abs(t_ref).astype(np.float32)).astype(np.float64)
+    dt = np.abs(t.astype(np.float64) - t_ref.astype(np.float64))
+    tol = ulp + 1025 * unit
+    assert np.all(dt <= tol), f"threshold off by {dt.max()} at {np.argmax(dt - tol)}"
+    light = np.abs(w.astype(np.float64)) * n <= np.abs(w.astype(np.float64)).sum() * (1 - 1e-12)
+    assert ulp_diff(t[light], t_ref[light]).max(initial=0) <= 1
+    mass, err = orc.reconstruct(w, t, a)
+    pos = w > 0
+    if pos.any():
+        assert err[pos].max() <= 1e-6
+    assert np.all(mass[~pos] == 0)
+
+
+@pytest.mark.parametrize("fam", FAMILIES)
+def test_build_plus_matches_oracle(wrs, orc, fam):
+    for n in SIZES:
+        w = family(fam, n, 300 + n)
+        if np.abs(w.astype(np.float64)).sum() == 0:
+            continue
+        say("build plus", fam, n)
+        t, a, st, *_ = gpu_build(wrs, w, plus=True)
+        assert st == wrs.OK
+        check_against_psaplus(orc, w, t, a)
+
+
+@pytest.mark.parametrize("fam", ["uniform", "power1"])
+def test_build_plus_2pow21(wrs, orc, fam):
+    """1024 greedy blocks; on power-law input the splitting stage gets several
+    hundred thousand items (many tiles and pack blocks)."""
+    w = family(fam, 1 << 21, 19)
+    say("build plus", fam, 1 << 21)
+    t, a, st, *_ = gpu_build(wrs, w, plus=True)
+    assert st == wrs.OK
+    check_against_psaplus(orc, w, t, a)
+
+
+def test_build_plus_repeat_is_deterministic(wrs):
+    """The same input twice in one workspace (stale staging and list contents
+    from the first call must not matter): identical tables."""
+    import torch
+    w_np = family("power1", 100003, 8)
+    dev = torch.device("cuda:0")
+    w = torch.from_numpy(w_np).to(dev)
+    ws = wrs.new_workspace(wrs.OP_BUILD_PLUS, w_np.size, 0, dev)
+    tabs = []
+    for rep in range(2):
+        say("build plus repeat", rep)
+        table = wrs.new_table(w_np.size, dev)
+        wrs.alias_build_plus(w, w_np.size, table, ws)
+        assert wrs.status(ws) == wrs.OK
+        tabs.append(table.cpu().numpy())
+    assert np.array_equal(tabs[0], tabs[1])
+
+
+def test_build_plus_domain_errors(wrs):
+    for bad in ([1.0, -1.0, 2.0], [1.0, float("nan")], [float("inf"), 1.0], [0.0, 0.0, 0.0]):
+        say("plus domain", bad)
+        *_, st, _, _, _ = gpu_build(wrs, np.array(bad, np.float32), plus=True)
+        assert st == wrs.EDOMAIN
+
+
+@pytest.mark.parametrize("fam", ["uniform", "power1"])
+def test_build_plus_full_size(wrs, orc, fam):
+    """n = 2^28 (seed 2): every item's mass within 1e-6 and 2^16 sampled light
+    buckets equal to n w_i / W correctly rounded."""
+    import workloads
+    n = 1 << 28
+    w = workloads.uniform(n, 2) if fam == "uniform" else workloads.power_law(n, 1.0, 2)
+    say("build plus full size", fam)
+    t, a, st, table, wt, ws = gpu_build(wrs, w, plus=True)
+    del table, wt, ws
+    assert st == wrs.OK
+    assert np.all((t >= 0) & (t <= 1)) and np.all((a >= 0) & (a < n))
+    mass, err = orc.reconstruct(w, t, a)
+    del mass
+    assert err.max() <= 1e-6, f"max relative mass error {err.max()} at {np.argmax(err)}"
+    idx = np.random.default_rng(5).integers(0, n, 1 << 16)
+    light, tl = orc.light_t_at(w, idx)
+    il = idx[light]
+    assert np.all(ulp_diff(t[il], tl[light]) <= 1)
