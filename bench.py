@@ -133,6 +133,10 @@ def main():
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
+        pws = wrs.new_workspace(wrs.OP_BUILD_PLUS, n, 0, dev)
+        for fam in inputs:
+            wrs.alias_build_plus(inputs[fam], n, table, pws)
+        del pws
         bench_wor(wrs, torch, np, workloads, reps=1)
         torch.cuda.synchronize()
         log(f"profile run done: build {tot_build / steps / 2:.3f} ms, sample {tot_sample / steps / 2:.3f} ms")
@@ -180,11 +184,42 @@ def main():
         result["roofline"]["traffic_gbs"] = round(tgbs, 1)
         result["roofline"]["traffic_frac"] = round(tgbs / HBM_PEAK_GBS, 4)
     if not args.skip_extras:
+        result["build_plus"] = bench_plus(wrs, torch, inputs, n, table)
         result["without_replacement"] = bench_wor(wrs, torch, np, workloads)
         result["batched"] = bench_batched(wrs, torch, np, workloads, not args.no_tune)
         result["served"] = bench_served(wrs, torch, np, workloads)
         result["cpu_baseline"] = bench_cpu(np, workloads)
     print(json.dumps(result), flush=True)
+
+
+def bench_plus(wrs, torch, inputs, n, table, reps=5):
+    """The greedy-block construction (PSA+, blocks of 2048 items) on the same
+    resident inputs: build time per family and the share of items its blocks
+    leave to the splitting stage.  The call waits for its greedy stage on the
+    host, so the wall clock around each call is reported too."""
+    dev = torch.device("cuda:0")
+    log("build plus")
+    ws = wrs.new_workspace(wrs.OP_BUILD_PLUS, n, 0, dev)
+    res = {"workload": "the same n=2^28 inputs, wrs_alias_build_plus (greedy blocks of 2048, then splitting)"}
+    for fam, w in inputs.items():
+        for _ in range(2):
+            wrs.alias_build_plus(w, n, table, ws)
+        torch.cuda.synchronize()
+        assert wrs.status(ws) == wrs.OK
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(reps):
+            wrs.alias_build_plus(w, n, table, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) * 1e3 / reps
+        ms = e0.elapsed_time(e1) / reps
+        left = wrs.plus_leftovers(ws)
+        res[fam] = {"ms": round(ms, 4), "wall_ms": round(wall_ms, 4), "gitems_s": round(n / (ms * 1e-3) / 1e9, 2),
+                    "left_fraction": round(left / n, 4)}
+    del ws
+    return res
 
 
 def bench_wor(wrs, torch, np, workloads, reps=5):

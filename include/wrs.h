@@ -95,6 +95,11 @@ int wrs_alias_build(const float* d_w, int64_t n, wrs_entry* d_table,
 int wrs_alias_build_plus(const float* d_w, int64_t n, wrs_entry* d_table,
                          void* d_ws, size_t ws_bytes, void* stream);
 
+/* After wrs_alias_build_plus on this workspace: the number of items its
+ * greedy blocks left to the splitting stage (0 if the weights were rejected).
+ * Synchronizes the stream, then reads one device word. */
+int wrs_plus_leftovers(const void* d_ws, void* stream, int64_t* nleft);
+
 /* Draw k samples with replacement from a table: d_out[s] = query at counter
  * c = first_counter + s, for s in [0, k).  One Philox block per draw with
  * key = seed and counter = (c low 32 bits, c high 32 bits, stream_id, 0):

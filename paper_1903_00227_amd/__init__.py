@@ -55,6 +55,7 @@ EXPORTS = {
                                        ctypes.c_size_t, ctypes.c_void_p]),
     "wrs_alias_build_plus": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_size_t, ctypes.c_void_p]),
+    "wrs_plus_leftovers": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "wrs_alias_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
                                         ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "wrs_sample_wor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
@@ -169,6 +170,13 @@ def alias_build_plus(w, n, table, ws, stream=None):
     """Greedy blocks, then the splitting construction on the items left
     (blocks the calling thread until the greedy stage has run)."""
     _check("wrs_alias_build_plus", lib().wrs_alias_build_plus(_ptr(w), n, _ptr(table), _ptr(ws), ws.numel() if hasattr(ws, "numel") else ws_bytes_of(ws), _stream(stream)))
+
+
+def plus_leftovers(ws, stream=None) -> int:
+    """Items the greedy blocks of the last alias_build_plus on ws left over."""
+    v = ctypes.c_int64()
+    _check("wrs_plus_leftovers", lib().wrs_plus_leftovers(_ptr(ws), _stream(stream), ctypes.byref(v)))
+    return v.value
 
 
 def ws_bytes_of(ws):

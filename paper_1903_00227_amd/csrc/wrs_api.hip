@@ -1,5 +1,6 @@
 // wrs_api.hip -- host side of the C ABI declared in include/wrs.h.
 #include <stdarg.h>
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -107,6 +108,15 @@ extern "C" int wrs_alias_build_plus(const float* d_w, int64_t n, wrs_entry* d_ta
     phase_blocks(L, blocks);
     e = launch_build(jl, blocks, st, true);
     if (e != hipSuccess) return dev_fail("wrs_alias_build_plus list launch", e);
+    return WRS_OK;
+}
+
+extern "C" int wrs_plus_leftovers(const void* d_ws, void* stream, int64_t* nleft) {
+    g_err[0] = 0;
+    if (!d_ws || !nleft) { set_error("wrs_plus_leftovers: null pointer"); return WRS_EINVAL; }
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipMemcpy(nleft, (const char*)d_ws + offsetof(BuildScalars, nleft), sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_fail("wrs_plus_leftovers", e);
     return WRS_OK;
 }
 

@@ -117,7 +117,7 @@ void build_list_layout(JobDesc& J, int64_t m) {
 
 // PSA+ workspace: the build workspace of n items, then the greedy arrays.
 struct PlusOffsets {
-    size_t cnt, goff, res, sidx, sw, lidx, lw, PI, total;
+    size_t cnt, goff, part, res, sidx, sw, lidx, lw, PI, total;
 };
 
 static PlusOffsets plus_offsets(int64_t n) {
@@ -127,6 +127,7 @@ static PlusOffsets plus_offsets(int64_t n) {
     size_t o = layout_for(n).total;
     P.cnt = o;  o = align256(o + sizeof(uint32_t) * G);
     P.goff = o; o = align256(o + sizeof(uint32_t) * G);
+    P.part = o; o = align256(o + sizeof(uint32_t) * cdiv(G, 512));
     P.res = o;  o = align256(o + sizeof(u128) * G);
     P.sidx = o; o = align256(o + sizeof(uint32_t) * G * GTILE);
     P.sw = o;   o = align256(o + sizeof(float) * G * GTILE);
@@ -145,6 +146,7 @@ PlusLayout plus_layout(void* ws, int64_t n) {
     PlusLayout P;
     P.cnt = (uint32_t*)(b + o.cnt);
     P.goff = (uint32_t*)(b + o.goff);
+    P.part = (uint32_t*)(b + o.part);
     P.res = (u128*)(b + o.res);
     P.sidx = (uint32_t*)(b + o.sidx);
     P.sw = (float*)(b + o.sw);
@@ -438,8 +440,9 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
         u128 sq = 0, sql = 0;
         int fh = FH_NONE;
         int smin = 0;
+        // (a zero weight, and a marker's 0, is 0 on the branch-free path too)
 #pragma unroll
-        for (int k = 0; k < 4 * AGG_VEC; ++k) smin = min(smin, grid_shift(qw(k), G));
+        for (int k = 0; k < 4 * AGG_VEC; ++k) smin = min(smin, qw(k) != 0.0f ? grid_shift(qw(k), G) : 0);
         if (__ballot(smin < 0) == 0) {
             // every weight of the tile lies on the grid
 #pragma unroll

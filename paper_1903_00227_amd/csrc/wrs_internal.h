@@ -124,6 +124,7 @@ void build_list_layout(JobDesc& J, int64_t m);
 struct PlusLayout {
     uint32_t* cnt;    // [G] items each greedy block left
     uint32_t* goff;   // [G] exclusive prefix of cnt
+    uint32_t* part;   // [ceil(G / 512)] sums of cnt over parts of 512 blocks
     u128* res;        // [G] exact n-scaled size of each block's residual item
     uint32_t* sidx;   // [G * GTILE] left items of block g at g * GTILE (index)
     float* sw;        // [G * GTILE] ... (weight or residual marker)

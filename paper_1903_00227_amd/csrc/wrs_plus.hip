@@ -168,10 +168,13 @@ __global__ __launch_bounds__(GTPB) void k_greedy(JobDesc J, PlusLayout P) {
                 if (ok) jlo = mid; else jhi = mid - 1;
             }
             int j = jlo, i = d0 - jlo;
-            // keys at the cursors: the next heavy to pack, and the deficit
-            // before the next light (Dt past the last light)
+            // keys at the cursors (the next heavy to pack, the deficit before
+            // the next light, Dt past the last light), and the key after each
+            // cursor read ahead, so no step waits for an LDS read
             uint64_t kb = (j < nHf) ? B[j] : ~0ull;
             uint64_t ka = (i < nL) ? A[i] : Dt;
+            uint64_t nb = (j + 1 < nHf) ? B[j + 1] : ~0ull;
+            uint64_t na = (i + 1 < nL) ? A[i + 1] : Dt;
             const double tscale = sc.tscale;
             for (int d = d0; d < d1; ++d) {
                 const bool take_h = (j < nHf) && (i >= nLf || kb <= ka);
@@ -183,10 +186,12 @@ __global__ __launch_bounds__(GTPB) void k_greedy(JobDesc J, PlusLayout P) {
                 store_entry(J.table, base + own, t, al);
                 if (take_h) {
                     ++j;
-                    kb = (j < nHf) ? B[j] : ~0ull;
+                    kb = nb;
+                    nb = (j + 1 < nHf) ? B[j + 1] : ~0ull;
                 } else {
                     ++i;
-                    ka = (i < nL) ? A[i] : Dt;
+                    ka = na;
+                    na = (i + 1 < nL) ? A[i + 1] : Dt;
                 }
             }
         }
@@ -250,34 +255,61 @@ __global__ __launch_bounds__(GTPB) void k_greedy(JobDesc J, PlusLayout P) {
     }
 }
 
-// Exclusive prefix of the blocks' left counts (one block), total into nleft.
-constexpr int LSCAN_TPB = 1024;
+// Exclusive prefix of the blocks' left counts, in two launches over parts of
+// LPART consecutive greedy blocks: part sums, then each part's prefix (from
+// the part sums before it) and its blocks' offsets; the total into nleft.
+constexpr int LPART = 512;  // greedy blocks per part (2 per thread)
+constexpr int LPART_TPB = 256;
 
-__global__ __launch_bounds__(LSCAN_TPB) void k_left_scan(BuildScalars* scp, const uint32_t* cnt, uint32_t* goff,
-                                                         int64_t G) {
-    __shared__ uint32_t s_w[LSCAN_TPB / 64];
-    if (scp->status != WRS_OK) {  // the greedy blocks did not run
-        if (threadIdx.x == 0) scp->nleft = 0;
-        return;
-    }
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t per = cdiv(G, LSCAN_TPB);
-    const int64_t s0 = (int64_t)tid * per, s1 = min(s0 + per, G);
-    uint32_t sum = 0;
-    for (int64_t b = s0; b < s1; ++b) sum += glb(cnt)[b];
-    const uint32_t inc = wave_incl_scan(sum);
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* s_w) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan(v);
     if (lane == 63) s_w[wv] = inc;
     __syncthreads();
-    uint32_t acc = inc - sum, tot = 0;
-    for (int q = 0; q < LSCAN_TPB / 64; ++q) {
-        if (q < wv) acc += s_w[q];
+    uint32_t tot = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) tot += s_w[q];
+    __syncthreads();
+    return tot;
+}
+
+__global__ __launch_bounds__(LPART_TPB) void k_left_part(const BuildScalars* scp, const uint32_t* cnt,
+                                                          uint32_t* part, int64_t G) {
+    __shared__ uint32_t s_w[LPART_TPB / 64];
+    if (scp->status != WRS_OK) return;
+    const int64_t b0 = (int64_t)blockIdx.x * LPART;
+    uint32_t v = 0;
+    for (int64_t b = b0 + threadIdx.x; b < min(b0 + LPART, G); b += LPART_TPB) v += glb(cnt)[b];
+    const uint32_t tot = block_sum_u32(v, s_w);
+    if (threadIdx.x == 0) glb(part)[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(LPART_TPB) void k_left_offsets(BuildScalars* scp, const uint32_t* cnt,
+                                                             const uint32_t* part, uint32_t* goff, int64_t G) {
+    __shared__ uint32_t s_w[LPART_TPB / 64];
+    if (scp->status != WRS_OK) {  // the greedy blocks did not run
+        if (blockIdx.x == 0 && threadIdx.x == 0) scp->nleft = 0;
+        return;
+    }
+    const int64_t P = gridDim.x;
+    // this part's offset: the part sums before it
+    uint32_t v = 0;
+    for (int64_t p = threadIdx.x; p < blockIdx.x; p += LPART_TPB) v += glb(part)[p];
+    const uint32_t before = block_sum_u32(v, s_w);
+    // scan of this part's counts, two consecutive blocks per thread
+    const int64_t b0 = (int64_t)blockIdx.x * LPART + 2 * threadIdx.x;
+    const uint32_t c0 = (b0 < G) ? glb(cnt)[b0] : 0u, c1 = (b0 + 1 < G) ? glb(cnt)[b0 + 1] : 0u;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan(c0 + c1);
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint32_t ex = before + inc - (c0 + c1), tot = before;
+    for (int q = 0; q < LPART_TPB / 64; ++q) {
+        if (q < wv) ex += s_w[q];
         tot += s_w[q];
     }
-    for (int64_t b = s0; b < s1; ++b) {
-        glb(goff)[b] = acc;
-        acc += glb(cnt)[b];
-    }
-    if (tid == 0) scp->nleft = (int64_t)tot;
+    if (b0 < G) glb(goff)[b0] = ex;
+    if (b0 + 1 < G) glb(goff)[b0 + 1] = ex + c0;
+    if (blockIdx.x == P - 1 && threadIdx.x == 0) scp->nleft = (int64_t)tot;
 }
 
 // Each block's left items to their place in the list.
@@ -298,7 +330,13 @@ hipError_t launch_greedy(const JobDesc& J, const PlusLayout& P, hipStream_t st) 
     hipLaunchKernelGGL(k_greedy, dim3((unsigned)G), dim3(GTPB), 0, st, J, P);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_left_scan, dim3(1), dim3(LSCAN_TPB), 0, st, J.sc, (const uint32_t*)P.cnt, P.goff, G);
+    const int64_t parts = cdiv(G, LPART);
+    hipLaunchKernelGGL(k_left_part, dim3((unsigned)parts), dim3(LPART_TPB), 0, st, (const BuildScalars*)J.sc,
+                       (const uint32_t*)P.cnt, P.part, G);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_left_offsets, dim3((unsigned)parts), dim3(LPART_TPB), 0, st, J.sc, (const uint32_t*)P.cnt,
+                       (const uint32_t*)P.part, P.goff, G);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_left_compact, dim3((unsigned)G), dim3(GTPB), 0, st, (const BuildScalars*)J.sc, P);

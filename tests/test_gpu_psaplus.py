@@ -78,6 +78,16 @@ def test_build_plus_2pow21(wrs, orc, fam):
     check_against_psaplus(orc, w, t, a)
 
 
+@pytest.mark.parametrize("fam", ["uniform", "power1", "equal", "one"])
+def test_build_plus_leftover_count(wrs, orc, fam):
+    """The number of items the greedy blocks leave equals the oracle's."""
+    w = family(fam, 100000, 41)
+    say("plus leftovers", fam)
+    *_, st, _, _, ws = gpu_build(wrs, w, plus=True)
+    assert st == wrs.OK
+    assert wrs.plus_leftovers(ws) == orc.psaplus_leftovers(w, BLOCK)
+
+
 def test_build_plus_repeat_is_deterministic(wrs):
     """The same input twice in one workspace (stale staging and list contents
     from the first call must not matter): identical tables."""
