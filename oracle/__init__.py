@@ -59,6 +59,7 @@ def _load():
         "orc_wor_keys": (ctypes.c_int, [P, i64, u64, u32, P]),
         "orc_wor_keys_at": (ctypes.c_int, [P, i64, u64, u32, P, i64, P]),
         "orc_sample_wor": (ctypes.c_int, [P, i64, i64, u64, u32, P, P]),
+        "orc_permutation": (ctypes.c_int, [P, i64, u64, u32, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -206,3 +207,12 @@ def sample_wor(w, k, seed, stream_id):
     _check("orc_sample_wor", _load().orc_sample_wor(_ptr(w), w.size, k, seed, stream_id, _ptr(out),
                                                     ctypes.byref(kth)))
     return out, kth.value
+
+
+def permutation(w, seed, stream_id):
+    """Problem WRP: every item, in ascending order of its exponential-clock key
+    (ties by index; zero weights last, in index order)."""
+    w = _f32(w)
+    out = np.empty(w.size, np.int32)
+    _check("orc_permutation", _load().orc_permutation(_ptr(w), w.size, seed, stream_id, _ptr(out)))
+    return out

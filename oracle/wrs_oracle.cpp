@@ -28,6 +28,7 @@
  *   orc_wor_keys,       exponential clocks (Section 2.3): key_i = -ln(u_i)/w_i,
  *   orc_sample_wor      the k smallest keys form the sample without replacement
  *                       (problem WRS-N of Section 1).
+ *   orc_permutation     problem WRP (Sections 1 and 7): all items in key order.
  *
  * Readings where the paper leaves details open are listed in the project's
  * design notes; the ones that affect results are repeated at the functions.
@@ -681,6 +682,25 @@ extern "C" int orc_wor_keys(const float* w, int64_t n, uint64_t seed, uint32_t s
         double e = -log(u);
         keys[i] = w[i] > 0.0f ? e / (double)w[i] : INFINITY;
     }
+    return ORC_OK;
+}
+
+/* Problem WRP (Section 1; Section 7): permute the items by the process of
+   WRS-N run to k = n.  By the exponential clocks of Section 2.3 that is the
+   order of the keys -ln(u_i)/w_i (the same keys as orc_wor_keys), ascending,
+   ties broken by the smaller index.  Reading: an item of weight 0 has key +inf,
+   so the zero-weight items follow every positive one, in index order. */
+extern "C" int orc_permutation(const float* w, int64_t n, uint64_t seed, uint32_t stream_id, int32_t* out) {
+    if (!w || !out || n < 1 || n > 2147483647LL) return ORC_EINVAL;
+    std::vector<double> keys((size_t)n);
+    int rc = orc_wor_keys(w, n, seed, stream_id, keys.data());
+    if (rc) return rc;
+    std::vector<int32_t> idx((size_t)n);
+    for (int64_t i = 0; i < n; ++i) idx[i] = (int32_t)i;
+    std::sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+        return keys[a] < keys[b] || (keys[a] == keys[b] && a < b);
+    });
+    memcpy(out, idx.data(), sizeof(int32_t) * (size_t)n);
     return ORC_OK;
 }
 
