@@ -53,14 +53,15 @@ enum {
     WRS_ENOTFOUND = -6  /* server: unknown table or request id */
 };
 
-enum { WRS_OP_BUILD = 1, WRS_OP_WOR = 2, WRS_OP_BUILD_PLUS = 3 };
+enum { WRS_OP_BUILD = 1, WRS_OP_WOR = 2, WRS_OP_BUILD_PLUS = 3, WRS_OP_PERM = 4 };
 
 /* Items per greedy block of wrs_alias_build_plus (part of its result). */
 #define WRS_PSAPLUS_BLOCK 2048
 
 /* Bytes of device workspace needed by wrs_alias_build (op = WRS_OP_BUILD, k
- * ignored), wrs_alias_build_plus (op = WRS_OP_BUILD_PLUS, k ignored) or
- * wrs_sample_wor (op = WRS_OP_WOR).  Depends on n (and k) only.
+ * ignored), wrs_alias_build_plus (op = WRS_OP_BUILD_PLUS, k ignored),
+ * wrs_sample_wor (op = WRS_OP_WOR) or wrs_permutation (op = WRS_OP_PERM, k
+ * ignored).  Depends on n (and k) only.
  * Returns 0 for invalid arguments. */
 size_t wrs_workspace_bytes(int op, int64_t n, int64_t k);
 
@@ -95,6 +96,20 @@ int wrs_alias_build(const float* d_w, int64_t n, wrs_entry* d_table,
 int wrs_alias_build_plus(const float* d_w, int64_t n, wrs_entry* d_table,
                          void* d_ws, size_t ws_bytes, void* stream);
 
+/* Weighted random permutation (problem WRP, Sections 1 and 7): d_out[0..n)
+ * receives every item once, in the order of the sequential process of
+ * sampling without replacement run to k = n.  Exponential clocks (Section
+ * 2.3): item i has key -ln(u_i)/w_i with u_i from the same Philox counters as
+ * wrs_sample_wor (so d_out[0..k) as a set is wrs_sample_wor's sample of size
+ * k), keys ascending, ties by the smaller index; zero-weight items come last,
+ * in index order.  d_w: n FP32 weights >= 0 (device).  d_out: n int32
+ * (device, 4-byte aligned).  d_ws: wrs_workspace_bytes(WRS_OP_PERM, n, 0)
+ * bytes (device, 256-byte aligned; about 25 bytes per item).  A negative, NaN
+ * or infinite weight sets the workspace status to WRS_EDOMAIN (wrs_status);
+ * d_out is then unspecified. */
+int wrs_permutation(const float* d_w, int64_t n, uint64_t seed, uint32_t stream_id, int32_t* d_out,
+                    void* d_ws, size_t ws_bytes, void* stream);
+
 /* After wrs_alias_build_plus on this workspace: the number of items its
  * greedy blocks left to the splitting stage (0 if the weights were rejected).
  * Synchronizes the stream, then reads one device word. */
@@ -121,7 +136,8 @@ int wrs_sample_wor(const float* d_w, int64_t n, int64_t k, uint64_t seed, uint32
                    int32_t* d_out, void* d_ws, size_t ws_bytes, void* stream);
 
 /* Synchronise `stream` and read the device status word of a workspace used by
- * wrs_alias_build or wrs_sample_wor.  *status_out is WRS_OK or an error code. */
+ * wrs_alias_build, wrs_alias_build_plus, wrs_sample_wor or wrs_permutation.
+ * *status_out is WRS_OK or an error code. */
 int wrs_status(const void* d_ws, void* stream, int* status_out);
 
 /* Synchronise `stream` and read the total weight W found by the last

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwrs.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EDEVICE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-OP_BUILD, OP_WOR, OP_BUILD_PLUS = 1, 2, 3
+OP_BUILD, OP_WOR, OP_BUILD_PLUS, OP_PERM = 1, 2, 3, 4
 PSAPLUS_BLOCK = 2048  # items per greedy block of alias_build_plus
 TUNE_BUILD, TUNE_SAMPLE = 1, 2
 
@@ -55,6 +55,8 @@ EXPORTS = {
                                        ctypes.c_size_t, ctypes.c_void_p]),
     "wrs_alias_build_plus": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_size_t, ctypes.c_void_p]),
+    "wrs_permutation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "wrs_plus_leftovers": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "wrs_alias_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
                                         ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
@@ -170,6 +172,11 @@ def alias_build_plus(w, n, table, ws, stream=None):
     """Greedy blocks, then the splitting construction on the items left
     (blocks the calling thread until the greedy stage has run)."""
     _check("wrs_alias_build_plus", lib().wrs_alias_build_plus(_ptr(w), n, _ptr(table), _ptr(ws), ws.numel() if hasattr(ws, "numel") else ws_bytes_of(ws), _stream(stream)))
+
+
+def permutation(w, n, seed, stream_id, out, ws, stream=None):
+    """Weighted random permutation of the n items into out (int32)."""
+    _check("wrs_permutation", lib().wrs_permutation(_ptr(w), n, seed, stream_id, _ptr(out), _ptr(ws), ws.numel() if hasattr(ws, "numel") else ws_bytes_of(ws), _stream(stream)))
 
 
 def plus_leftovers(ws, stream=None) -> int:

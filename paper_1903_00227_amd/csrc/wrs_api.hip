@@ -39,6 +39,7 @@ extern "C" size_t wrs_workspace_bytes(int op, int64_t n, int64_t k) {
     if (n < 1 || n > N_MAX || k < 0) return 0;
     if (op == WRS_OP_BUILD) return build_ws_bytes(n);
     if (op == WRS_OP_BUILD_PLUS) return plus_ws_bytes(n);
+    if (op == WRS_OP_PERM) return perm_ws_bytes(n);
     if (op == WRS_OP_WOR) return wor_ws_bytes(n, k);
     return 0;
 }
@@ -111,6 +112,19 @@ extern "C" int wrs_alias_build_plus(const float* d_w, int64_t n, wrs_entry* d_ta
     return WRS_OK;
 }
 
+extern "C" int wrs_permutation(const float* d_w, int64_t n, uint64_t seed, uint32_t stream_id, int32_t* d_out,
+                               void* d_ws, size_t ws_bytes, void* stream) {
+    g_err[0] = 0;
+    if (!d_w || !d_out || !d_ws) { set_error("wrs_permutation: null pointer"); return WRS_EINVAL; }
+    if (n < 1 || n > N_MAX) { set_error("wrs_permutation: n = %lld out of [1, 2^31-1]", (long long)n); return WRS_EINVAL; }
+    if (ws_bytes < perm_ws_bytes(n)) { set_error("wrs_permutation: workspace %zu < %zu bytes", ws_bytes, perm_ws_bytes(n)); return WRS_EINVAL; }
+    if (((uintptr_t)d_ws) & 255) { set_error("wrs_permutation: workspace not 256-byte aligned"); return WRS_EINVAL; }
+    if (((uintptr_t)d_out) & 3) { set_error("wrs_permutation: output not 4-byte aligned"); return WRS_EINVAL; }
+    const int e = launch_perm(d_w, n, seed, stream_id, d_out, d_ws, (hipStream_t)stream);
+    if (e != 0) return dev_fail("wrs_permutation launch", (hipError_t)e);
+    return WRS_OK;
+}
+
 extern "C" int wrs_plus_leftovers(const void* d_ws, void* stream, int64_t* nleft) {
     g_err[0] = 0;
     if (!d_ws || !nleft) { set_error("wrs_plus_leftovers: null pointer"); return WRS_EINVAL; }
@@ -178,7 +192,7 @@ static int read_ws(const void* d_ws, size_t off, void* dst, size_t bytes, void* 
 extern "C" int wrs_status(const void* d_ws, void* stream, int* status_out) {
     g_err[0] = 0;
     if (!d_ws || !status_out) { set_error("wrs_status: null pointer"); return WRS_EINVAL; }
-    // Both the build and the WOR workspaces start with their status word.
+    // The build, PSA+, WOR and permutation workspaces all start with their status word.
     int s = 0;
     int rc = read_ws(d_ws, 0, &s, sizeof s, stream);
     if (rc) return rc;

@@ -447,4 +447,18 @@ __device__ __forceinline__ float heavy_t(uint64_t E, uint64_t D, double tscale) 
     return fminf(fmaxf(t, 0.0f), 1.0f);
 }
 
+// ---------------------------------------------------------------------------
+// Exponential clocks (Section 2.3): the variate -ln(u) of item i, u from the
+// Philox counter (i, stream id, 1).  Shared by sampling without replacement
+// and the weighted permutation, so both order items by the same keys.
+// ---------------------------------------------------------------------------
+// -ln(u) for u = (x0 + 1) 2^-32, accurate near u = 1 through log1p.
+__device__ __forceinline__ double neg_log_u(uint32_t x0) {
+    if (x0 >= 0x7FFFFFFFu) {  // u >= 1/2
+        const double d = (double)(0xFFFFFFFFu - x0) * (1.0 / 4294967296.0);  // 1 - u, exact
+        return -log1p(-d);
+    }
+    return -log(((double)x0 + 1.0) * (1.0 / 4294967296.0));
+}
+
 }  // namespace wrs

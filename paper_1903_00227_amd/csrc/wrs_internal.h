@@ -163,6 +163,10 @@ int launch_wor(const float* w, int64_t n, int64_t k, uint64_t seed, uint32_t sid
                void* ws, hipStream_t st);
 int wor_status_offset();
 
+// Weighted permutation (returns 0 or a hipError_t)
+size_t perm_ws_bytes(int64_t n);
+int launch_perm(const float* w, int64_t n, uint64_t seed, uint32_t sid, int32_t* out, void* ws, hipStream_t st);
+
 // Error reporting for the C ABI.
 void set_error(const char* fmt, ...);
 

@@ -1,0 +1,363 @@
+// wrs_perm.hip -- weighted random permutation (problem WRP, Sections 1 and 7).
+//
+// WRP permutes the items by the process of sampling without replacement run
+// to k = n.  With the exponential clocks of Section 2.3 that is the order of
+// the keys -ln(u_i)/w_i (ties by index), and Section 7 reduces it to sorting
+// random keys; its bucketing makes buckets of constant expected occupancy for
+// any weights.  Here the keys are the WOR keys in FP64 (the same Philox
+// counters, the same -ln u), so the permutation's first k items are the WOR
+// sample of size k.  The sort is a stable LSD radix sort over the top 40 bits
+// of the keys' bit patterns (non-negative doubles order like their bits): the
+// top bits of a double are a piecewise-linear log2 of it, the same kind of
+// scale as the paper's logarithmic bucket map, so runs of equal top bits hold
+// a constant expected number of items.  Starting from index order, the stable
+// passes leave each run in index order; a last pass orders the runs of two or
+// more items by their full keys.
+//
+// Per pass (digit = 8 bits): an upsweep counts each block's digits, a flat
+// exclusive scan over the digit-major counts gives every (digit, block) its
+// output offset, and a downsweep ranks the block's items stably (ballots over
+// the digit bits inside each wave, wave and block prefixes in LDS), reorders
+// them in LDS by digit and writes each digit's run contiguously.
+#include "wrs_device.h"
+
+namespace wrs {
+
+constexpr int RS_TPB = 512;              // threads per radix block
+constexpr int RS_IPT = 8;                // items per thread
+constexpr int RS_TILE = RS_TPB * RS_IPT; // 4096 items per block
+constexpr int RS_WAVES = RS_TPB / 64;
+constexpr int RS_WITEMS = RS_IPT * 64;   // consecutive items of one wave
+constexpr int RS_PASSES = 5;             // digits at bits 24..63
+constexpr int RS_LOW = 24;               // bits below the sorted digits
+constexpr int SC_TPB = 256, SC_PER = 8, SC_PART = SC_TPB * SC_PER;
+
+struct PermScalars {
+    int32_t status;
+    int32_t pad[63];
+};
+
+struct PermLayout {
+    PermScalars* sc;
+    uint64_t* kA;
+    uint64_t* kB;
+    uint32_t* vA;
+    uint32_t* vB;
+    uint32_t* cnt;   // [256 * NB] digit-major block counts
+    uint32_t* off;   // [256 * NB] their exclusive prefix
+    uint32_t* part;  // [ceil(256 * NB / SC_PART)]
+};
+
+static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct PermOffsets {
+    size_t kA, kB, vA, vB, cnt, off, part, total;
+};
+
+static PermOffsets perm_offsets(int64_t n) {
+    const int64_t NB = cdiv(n, RS_TILE);
+    const int64_t L = 256 * NB;
+    PermOffsets o;
+    size_t p = a256(sizeof(PermScalars));
+    o.kA = p;   p = a256(p + sizeof(uint64_t) * n);
+    o.kB = p;   p = a256(p + sizeof(uint64_t) * n);
+    o.vA = p;   p = a256(p + sizeof(uint32_t) * n);
+    o.vB = p;   p = a256(p + sizeof(uint32_t) * n);
+    o.cnt = p;  p = a256(p + sizeof(uint32_t) * L);
+    o.off = p;  p = a256(p + sizeof(uint32_t) * L);
+    o.part = p; p = a256(p + sizeof(uint32_t) * cdiv(L, SC_PART));
+    o.total = p;
+    return o;
+}
+
+size_t perm_ws_bytes(int64_t n) { return perm_offsets(n).total; }
+
+static PermLayout perm_layout(void* ws, int64_t n) {
+    const PermOffsets o = perm_offsets(n);
+    char* b = (char*)ws;
+    PermLayout P;
+    P.sc = (PermScalars*)b;
+    P.kA = (uint64_t*)(b + o.kA);
+    P.kB = (uint64_t*)(b + o.kB);
+    P.vA = (uint32_t*)(b + o.vA);
+    P.vB = (uint32_t*)(b + o.vB);
+    P.cnt = (uint32_t*)(b + o.cnt);
+    P.off = (uint32_t*)(b + o.off);
+    P.part = (uint32_t*)(b + o.part);
+    return P;
+}
+
+__global__ void k_perm_init(PermScalars* sc) {
+    if (threadIdx.x == 0) sc->status = WRS_OK;
+}
+
+// Key of every item: bits of -ln(u_i)/w_i (+inf for a zero weight), value i.
+__global__ __launch_bounds__(256) void k_perm_keys(const float* w, int64_t n, uint64_t seed, uint32_t sid,
+                                                   uint64_t* keys, uint32_t* vals, PermScalars* sc) {
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        const float raw = glb(w)[i];
+        const bool bad = !(raw >= 0.0f) || isinf(raw);  // on the weight as given (-0 passes)
+        const float v = canonical_weight(raw);
+        const uint4 x = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)((uint64_t)i >> 32), sid, 1u),
+                                      (uint32_t)seed, (uint32_t)(seed >> 32));
+        const double key = (v > 0.0f) ? neg_log_u(x.x) / (double)v : INFINITY;
+        glb(keys)[i] = (uint64_t)__double_as_longlong(key);
+        glb(vals)[i] = (uint32_t)i;
+        if (bad) s_bad = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_bad) atomicExch(&sc->status, (int32_t)WRS_EDOMAIN);
+}
+
+// Digit counts of each block of RS_TILE items, digit-major: cnt[d * NB + b].
+__global__ __launch_bounds__(RS_TPB) void k_rs_up(const uint64_t* keys, int64_t n, int sh, uint32_t* cnt,
+                                                  int64_t NB) {
+    __shared__ uint32_t s_h[256];
+    if (threadIdx.x < 256) s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int c = (int)min((int64_t)RS_TILE, n - base);
+    for (int p = threadIdx.x; p < c; p += RS_TPB) atomicAdd(&s_h[(uint32_t)(glb(keys)[base + p] >> sh) & 255u], 1u);
+    __syncthreads();
+    if (threadIdx.x < 256) glb(cnt)[(int64_t)threadIdx.x * NB + blockIdx.x] = s_h[threadIdx.x];
+}
+
+// Flat exclusive scan of a u32 array: part sums, their scan, then each part.
+__global__ __launch_bounds__(SC_TPB) void k_scan_reduce(const uint32_t* in, int64_t L, uint32_t* part) {
+    __shared__ uint32_t s_w[SC_TPB / 64];
+    const int64_t p0 = (int64_t)blockIdx.x * SC_PART;
+    uint32_t v = 0;
+    for (int64_t i = p0 + threadIdx.x; i < min(p0 + SC_PART, L); i += SC_TPB) v += glb(in)[i];
+    const uint32_t inc = wave_incl_scan(v);
+    if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int q = 0; q < SC_TPB / 64; ++q) t += s_w[q];
+        glb(part)[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* part, int64_t P) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < P; b0 += 1024) {
+        const int64_t i = b0 + tid;
+        const uint32_t v = (i < P) ? glb(part)[i] : 0u;
+        const uint32_t inc = wave_incl_scan(v);
+        if (lane == 63) s_w[wv] = inc;
+        __syncthreads();
+        uint32_t ex = s_carry + inc - v, tot = 0;
+        for (int q = 0; q < 16; ++q) {
+            if (q < wv) ex += s_w[q];
+            tot += s_w[q];
+        }
+        if (i < P) glb(part)[i] = ex;
+        __syncthreads();  // every thread has read s_w and s_carry
+        if (tid == 0) s_carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(SC_TPB) void k_scan_apply(const uint32_t* in, uint32_t* out, int64_t L,
+                                                       const uint32_t* part) {
+    __shared__ uint32_t s_w[SC_TPB / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * SC_PART + (int64_t)tid * SC_PER;
+    uint32_t v[SC_PER];
+    uint32_t s = 0;
+#pragma unroll
+    for (int e = 0; e < SC_PER; ++e) {
+        v[e] = (i0 + e < L) ? glb(in)[i0 + e] : 0u;
+        s += v[e];
+    }
+    const uint32_t inc = wave_incl_scan(s);
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint32_t ex = glb(part)[blockIdx.x] + inc - s;
+    for (int q = 0; q < wv; ++q) ex += s_w[q];
+#pragma unroll
+    for (int e = 0; e < SC_PER; ++e) {
+        if (i0 + e < L) glb(out)[i0 + e] = ex;
+        ex += v[e];
+    }
+}
+
+// One stable pass on the digit at bit sh.
+__global__ __launch_bounds__(RS_TPB) void k_rs_down(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                    uint32_t* vout, const uint32_t* off, int64_t n, int sh,
+                                                    int64_t NB) {
+    __shared__ uint32_t s_wc[RS_WAVES][256];  // per-wave digit counts, then each wave's start
+    __shared__ uint32_t s_dstart[256];        // block-local start of each digit
+    __shared__ uint32_t s_goff[256];          // global start of this block's items of each digit
+    __shared__ uint32_t s_tmp[RS_WAVES];
+    __shared__ uint64_t s_key[RS_TILE];
+    __shared__ uint32_t s_val[RS_TILE];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t b = blockIdx.x, base = b * RS_TILE;
+    const int c = (int)min((int64_t)RS_TILE, n - base);
+    for (int q = tid; q < RS_WAVES * 256; q += RS_TPB) (&s_wc[0][0])[q] = 0;
+    if (tid < 256) s_goff[tid] = glb(off)[(int64_t)tid * NB + b];
+    __syncthreads();
+    uint64_t key[RS_IPT];
+    uint32_t val[RS_IPT], rk[RS_IPT];
+    const uint64_t lt = (1ull << lane) - 1ull;
+    // rank inside the wave: the wave's items in order, 64 per round
+#pragma unroll
+    for (int r = 0; r < RS_IPT; ++r) {
+        const int p = wv * RS_WITEMS + r * 64 + lane;
+        const bool valid = p < c;
+        key[r] = valid ? glb(kin)[base + p] : ~0ull;
+        val[r] = valid ? glb(vin)[base + p] : 0u;
+        const uint32_t dg = (uint32_t)(key[r] >> sh) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t bb = __ballot((dg >> bit) & 1u);
+            peers &= ((dg >> bit) & 1u) ? bb : ~bb;
+        }
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        // every peer reads the count before its lowest lane writes the new
+        // one (one wave: its LDS accesses run in program order)
+        const uint32_t before = valid ? s_wc[wv][dg] : 0u;
+        rk[r] = before + below;
+        if (valid && below == 0) s_wc[wv][dg] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // digit starts in the block, and each wave's start inside its digit
+    // (threads 0..255 own one digit each; every thread reaches each barrier)
+    uint32_t cw[RS_WAVES], tot = 0;
+    if (tid < 256) {
+#pragma unroll
+        for (int q = 0; q < RS_WAVES; ++q) {
+            cw[q] = s_wc[q][tid];
+            tot += cw[q];
+        }
+    }
+    const uint32_t inc = wave_incl_scan(tot);
+    if (lane == 63) s_tmp[wv] = inc;
+    __syncthreads();
+    if (tid < 256) {
+        uint32_t ex = inc - tot;
+        for (int q = 0; q < wv; ++q) ex += s_tmp[q];
+        s_dstart[tid] = ex;
+#pragma unroll
+        for (int q = 0; q < RS_WAVES; ++q) {  // column tid: read above by this thread only
+            s_wc[q][tid] = ex;
+            ex += cw[q];
+        }
+    }
+    __syncthreads();
+    // the block's items in digit order, stable
+#pragma unroll
+    for (int r = 0; r < RS_IPT; ++r) {
+        const int p = wv * RS_WITEMS + r * 64 + lane;
+        if (p < c) {
+            const uint32_t dg = (uint32_t)(key[r] >> sh) & 255u;
+            const uint32_t lp = s_wc[wv][dg] + rk[r];
+            s_key[lp] = key[r];
+            s_val[lp] = val[r];
+        }
+    }
+    __syncthreads();
+    // each digit's run to its global place (consecutive threads, consecutive slots)
+    for (int q = tid; q < c; q += RS_TPB) {
+        const uint64_t k = s_key[q];
+        const uint32_t dg = (uint32_t)(k >> sh) & 255u;
+        const int64_t g = (int64_t)s_goff[dg] + (q - (int32_t)s_dstart[dg]);
+        glb(kout)[g] = k;
+        glb(vout)[g] = s_val[q];
+    }
+}
+
+// Runs of two or more items with equal sorted bits, ordered by the full key
+// and then the index (a run is in index order after the stable passes; runs
+// hold a constant expected number of items).  A run of +inf keys (zero
+// weights) is already in index order.  The sorted keys are only read here, so
+// every thread finds the same runs; the thread of a run's first item copies
+// the run's keys to the same positions of the idle key buffer and sorts them
+// there together with the run's indices (runs are disjoint).
+__global__ __launch_bounds__(256) void k_rs_fix(const uint64_t* keys, uint64_t* scratch, uint32_t* vals,
+                                                int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const WRS_GLOBAL uint64_t* K = glb(keys);
+    WRS_GLOBAL uint64_t* S = glb(scratch);
+    WRS_GLOBAL uint32_t* V = glb(vals);
+    const uint64_t k = K[i];
+    const uint64_t top = k >> RS_LOW;
+    if ((k >> 52) >= 0x7FFull) return;  // +inf (or NaN on rejected input): nothing to order
+    if (i > 0 && (K[i - 1] >> RS_LOW) == top) return;
+    if (i + 1 >= n || (K[i + 1] >> RS_LOW) != top) return;
+    int64_t e = i + 2;
+    while (e < n && (K[e] >> RS_LOW) == top) ++e;
+    for (int64_t a = i; a < e; ++a) S[a] = K[a];
+    for (int64_t a = i + 1; a < e; ++a) {  // insertion sort by (key, index)
+        const uint64_t ka = S[a];
+        const uint32_t va = V[a];
+        int64_t j = a - 1;
+        while (j >= i && (S[j] > ka || (S[j] == ka && V[j] > va))) {
+            S[j + 1] = S[j];
+            V[j + 1] = V[j];
+            --j;
+        }
+        S[j + 1] = ka;
+        V[j + 1] = va;
+    }
+}
+
+int launch_perm(const float* d_w, int64_t n, uint64_t seed, uint32_t sid, int32_t* d_out, void* ws,
+                hipStream_t st) {
+    const PermLayout P = perm_layout(ws, n);
+    const int64_t NB = cdiv(n, RS_TILE);
+    const int64_t L = 256 * NB;
+    const int64_t parts = cdiv(L, SC_PART);
+#define WRS_CHECK()                                      \
+    do {                                                 \
+        hipError_t e_ = hipGetLastError();               \
+        if (e_ != hipSuccess) return (int)e_;            \
+    } while (0)
+    hipLaunchKernelGGL(k_perm_init, dim3(1), dim3(64), 0, st, P.sc);
+    WRS_CHECK();
+    hipLaunchKernelGGL(k_perm_keys, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, d_w, n, seed, sid, P.kA, P.vA,
+                       P.sc);
+    WRS_CHECK();
+    uint64_t* kin = P.kA;
+    uint32_t* vin = P.vA;
+    for (int pass = 0; pass < RS_PASSES; ++pass) {
+        const int sh = RS_LOW + 8 * pass;
+        const bool last = pass == RS_PASSES - 1;
+        uint64_t* kout = (kin == P.kA) ? P.kB : P.kA;
+        uint32_t* vout = last ? (uint32_t*)d_out : ((vin == P.vA) ? P.vB : P.vA);
+        hipLaunchKernelGGL(k_rs_up, dim3((unsigned)NB), dim3(RS_TPB), 0, st, (const uint64_t*)kin, n, sh, P.cnt, NB);
+        WRS_CHECK();
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)parts), dim3(SC_TPB), 0, st, (const uint32_t*)P.cnt, L,
+                           P.part);
+        WRS_CHECK();
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, P.part, parts);
+        WRS_CHECK();
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)parts), dim3(SC_TPB), 0, st, (const uint32_t*)P.cnt, P.off,
+                           L, (const uint32_t*)P.part);
+        WRS_CHECK();
+        hipLaunchKernelGGL(k_rs_down, dim3((unsigned)NB), dim3(RS_TPB), 0, st, (const uint64_t*)kin,
+                           (const uint32_t*)vin, kout, vout, (const uint32_t*)P.off, n, sh, NB);
+        WRS_CHECK();
+        kin = kout;
+        vin = vout;
+    }
+    uint64_t* idle = (kin == P.kA) ? P.kB : P.kA;
+    hipLaunchKernelGGL(k_rs_fix, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, (const uint64_t*)kin, idle,
+                       (uint32_t*)d_out, n);
+    WRS_CHECK();
+#undef WRS_CHECK
+    return 0;
+}
+
+}  // namespace wrs

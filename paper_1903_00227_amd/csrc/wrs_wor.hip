@@ -126,14 +126,6 @@ __device__ __forceinline__ uint32_t wor_x0(const WorArgs& A, int64_t i) {
     return x.x;
 }
 
-// -ln(u) for u = (x0 + 1) 2^-32, accurate near u = 1 through log1p.
-__device__ __forceinline__ double neg_log_u(uint32_t x0) {
-    if (x0 >= 0x7FFFFFFFu) {  // u >= 1/2
-        const double d = (double)(0xFFFFFFFFu - x0) * (1.0 / 4294967296.0);  // 1 - u, exact
-        return -log1p(-d);
-    }
-    return -log(((double)x0 + 1.0) * (1.0 / 4294967296.0));
-}
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_wor_tau(WorArgs A) {

@@ -80,3 +80,18 @@ def test_build_plus_host_validation(wrs):
     assert "aligned" in wrs.last_error()
     assert L.wrs_alias_build_plus(fake, n, ctypes.c_void_p((1 << 20) + 4), fake, plus, None) == wrs.EINVAL
     assert wrs.PSAPLUS_BLOCK == 2048
+
+
+def test_permutation_host_validation(wrs):
+    L = wrs.lib()
+    n = 100000
+    nb = L.wrs_workspace_bytes(wrs.OP_PERM, n, 0)
+    assert nb >= 24 * n  # two key and two index buffers
+    assert L.wrs_workspace_bytes(wrs.OP_PERM, 0, 0) == 0
+    assert L.wrs_permutation(None, n, 0, 0, None, None, 0, None) == wrs.EINVAL
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every check below fails on the host
+    assert L.wrs_permutation(fake, 0, 0, 0, fake, fake, nb, None) == wrs.EINVAL
+    assert L.wrs_permutation(fake, n, 0, 0, fake, fake, nb - 1, None) == wrs.EINVAL
+    assert "workspace" in wrs.last_error()
+    assert L.wrs_permutation(fake, n, 0, 0, fake, ctypes.c_void_p((1 << 20) + 16), nb, None) == wrs.EINVAL
+    assert L.wrs_permutation(fake, n, 0, 0, ctypes.c_void_p((1 << 20) + 2), fake, nb, None) == wrs.EINVAL
