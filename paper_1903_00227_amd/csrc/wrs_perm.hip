@@ -30,7 +30,7 @@ constexpr int RS_WAVES = RS_TPB / 64;
 constexpr int RS_WITEMS = RS_IPT * 64;   // consecutive items of one wave
 constexpr int RS_PASSES = 5;             // digits at bits 24..63
 constexpr int RS_LOW = 24;               // bits below the sorted digits
-constexpr int SC_TPB = 256, SC_PER = 8, SC_PART = SC_TPB * SC_PER;
+constexpr int CH = 64;                   // radix blocks per chunk of the count scan
 
 struct PermScalars {
     int32_t status;
@@ -43,15 +43,16 @@ struct PermLayout {
     uint64_t* kB;
     uint32_t* vA;
     uint32_t* vB;
-    uint32_t* cnt;   // [256 * NB] digit-major block counts
-    uint32_t* off;   // [256 * NB] their exclusive prefix
-    uint32_t* part;  // [ceil(256 * NB / SC_PART)]
+    uint32_t* cnt;   // [NB * 256] block-major digit counts: cnt[b * 256 + d]
+    uint32_t* off;   // [NB * 256] output offset of block b's items of digit d
+    uint32_t* part;  // [NC * 256] chunk column sums, then their column prefixes
+    uint32_t* tot;   // [256] items of each digit
 };
 
 static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct PermOffsets {
-    size_t kA, kB, vA, vB, cnt, off, part, total;
+    size_t kA, kB, vA, vB, cnt, off, part, tot, total;
 };
 
 static PermOffsets perm_offsets(int64_t n) {
@@ -65,7 +66,8 @@ static PermOffsets perm_offsets(int64_t n) {
     o.vB = p;   p = a256(p + sizeof(uint32_t) * n);
     o.cnt = p;  p = a256(p + sizeof(uint32_t) * L);
     o.off = p;  p = a256(p + sizeof(uint32_t) * L);
-    o.part = p; p = a256(p + sizeof(uint32_t) * cdiv(L, SC_PART));
+    o.part = p; p = a256(p + sizeof(uint32_t) * 256 * cdiv(NB, CH));
+    o.tot = p;  p = a256(p + sizeof(uint32_t) * 256);
     o.total = p;
     return o;
 }
@@ -84,6 +86,7 @@ static PermLayout perm_layout(void* ws, int64_t n) {
     P.cnt = (uint32_t*)(b + o.cnt);
     P.off = (uint32_t*)(b + o.off);
     P.part = (uint32_t*)(b + o.part);
+    P.tot = (uint32_t*)(b + o.tot);
     return P;
 }
 
@@ -113,80 +116,100 @@ __global__ __launch_bounds__(256) void k_perm_keys(const float* w, int64_t n, ui
     if (threadIdx.x == 0 && s_bad) atomicExch(&sc->status, (int32_t)WRS_EDOMAIN);
 }
 
-// Digit counts of each block of RS_TILE items, digit-major: cnt[d * NB + b].
-__global__ __launch_bounds__(RS_TPB) void k_rs_up(const uint64_t* keys, int64_t n, int sh, uint32_t* cnt,
+// Lanes of the wave whose valid item has digit dg (ballots over its 8 bits).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t dg, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const uint64_t bb = __ballot((dg >> bit) & 1u);
+        peers &= ((dg >> bit) & 1u) ? bb : ~bb;
+    }
+    return peers;
+}
+
+// Digit counts of each block of RS_TILE items, block-major: cnt[b * 256 + d].
+// 256 threads with 16 loads each keep more bytes in flight per CU than the
+// downsweep's shape; a wave adds one count per distinct digit and round.
+constexpr int UP_TPB = 256, UP_IPT = RS_TILE / UP_TPB;
+
+__global__ __launch_bounds__(UP_TPB) void k_rs_up(const uint64_t* keys, int64_t n, int sh, uint32_t* cnt,
                                                   int64_t NB) {
     __shared__ uint32_t s_h[256];
-    if (threadIdx.x < 256) s_h[threadIdx.x] = 0;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    s_h[tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     const int c = (int)min((int64_t)RS_TILE, n - base);
-    for (int p = threadIdx.x; p < c; p += RS_TPB) atomicAdd(&s_h[(uint32_t)(glb(keys)[base + p] >> sh) & 255u], 1u);
-    __syncthreads();
-    if (threadIdx.x < 256) glb(cnt)[(int64_t)threadIdx.x * NB + blockIdx.x] = s_h[threadIdx.x];
-}
-
-// Flat exclusive scan of a u32 array: part sums, their scan, then each part.
-__global__ __launch_bounds__(SC_TPB) void k_scan_reduce(const uint32_t* in, int64_t L, uint32_t* part) {
-    __shared__ uint32_t s_w[SC_TPB / 64];
-    const int64_t p0 = (int64_t)blockIdx.x * SC_PART;
-    uint32_t v = 0;
-    for (int64_t i = p0 + threadIdx.x; i < min(p0 + SC_PART, L); i += SC_TPB) v += glb(in)[i];
-    const uint32_t inc = wave_incl_scan(v);
-    if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = inc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int q = 0; q < SC_TPB / 64; ++q) t += s_w[q];
-        glb(part)[blockIdx.x] = t;
+    uint64_t key[UP_IPT];
+#pragma unroll
+    for (int r = 0; r < UP_IPT; ++r) {
+        const int p = wv * (UP_IPT * 64) + r * 64 + lane;
+        key[r] = (p < c) ? glb(keys)[base + p] : 0ull;
     }
+    const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int r = 0; r < UP_IPT; ++r) {
+        const int p = wv * (UP_IPT * 64) + r * 64 + lane;
+        const bool valid = p < c;
+        const uint32_t dg = (uint32_t)(key[r] >> sh) & 255u;
+        const uint64_t peers = digit_peers(dg, valid);
+        if (valid && (peers & lt) == 0) atomicAdd(&s_h[dg], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    glb(cnt)[(int64_t)blockIdx.x * 256 + tid] = s_h[tid];
 }
 
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* part, int64_t P) {
-    __shared__ uint32_t s_w[16];
-    __shared__ uint32_t s_carry;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+// Output offsets off[b][d] = (items of digits below d) + (items of digit d in
+// blocks before b), from the block-major counts: column sums over chunks of
+// CH blocks (coalesced over d), one block per digit scans its column over the
+// chunks, then each chunk adds the digit starts and its running sums.
+__global__ __launch_bounds__(256) void k_col_part(const uint32_t* cnt, int64_t NB, uint32_t* part) {
+    const int d = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * CH;
+    uint32_t s = 0;
+    for (int64_t b = b0; b < min(b0 + CH, NB); ++b) s += glb(cnt)[b * 256 + d];
+    glb(part)[(int64_t)blockIdx.x * 256 + d] = s;
+}
+
+__global__ __launch_bounds__(256) void k_col_scan(uint32_t* part, int64_t NC, uint32_t* tot) {
+    __shared__ uint32_t s_w[4], s_carry;
+    const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid == 0) s_carry = 0;
     __syncthreads();
-    for (int64_t b0 = 0; b0 < P; b0 += 1024) {
-        const int64_t i = b0 + tid;
-        const uint32_t v = (i < P) ? glb(part)[i] : 0u;
+    for (int64_t c0 = 0; c0 < NC; c0 += 256) {
+        const int64_t c = c0 + tid;
+        const uint32_t v = (c < NC) ? glb(part)[c * 256 + d] : 0u;
         const uint32_t inc = wave_incl_scan(v);
         if (lane == 63) s_w[wv] = inc;
         __syncthreads();
-        uint32_t ex = s_carry + inc - v, tot = 0;
-        for (int q = 0; q < 16; ++q) {
+        uint32_t ex = s_carry + inc - v, t = 0;
+        for (int q = 0; q < 4; ++q) {
             if (q < wv) ex += s_w[q];
-            tot += s_w[q];
+            t += s_w[q];
         }
-        if (i < P) glb(part)[i] = ex;
-        __syncthreads();  // every thread has read s_w and s_carry
-        if (tid == 0) s_carry += tot;
+        if (c < NC) glb(part)[c * 256 + d] = ex;
+        __syncthreads();
+        if (tid == 0) s_carry += t;
         __syncthreads();
     }
+    if (tid == 0) glb(tot)[d] = s_carry;
 }
 
-__global__ __launch_bounds__(SC_TPB) void k_scan_apply(const uint32_t* in, uint32_t* out, int64_t L,
-                                                       const uint32_t* part) {
-    __shared__ uint32_t s_w[SC_TPB / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t i0 = (int64_t)blockIdx.x * SC_PART + (int64_t)tid * SC_PER;
-    uint32_t v[SC_PER];
-    uint32_t s = 0;
-#pragma unroll
-    for (int e = 0; e < SC_PER; ++e) {
-        v[e] = (i0 + e < L) ? glb(in)[i0 + e] : 0u;
-        s += v[e];
-    }
-    const uint32_t inc = wave_incl_scan(s);
+__global__ __launch_bounds__(256) void k_col_apply(const uint32_t* cnt, const uint32_t* part, const uint32_t* tot,
+                                                   int64_t NB, uint32_t* off) {
+    __shared__ uint32_t s_w[4];
+    const int d = threadIdx.x, lane = d & 63, wv = d >> 6;
+    const uint32_t t = glb(tot)[d];
+    const uint32_t inc = wave_incl_scan(t);
     if (lane == 63) s_w[wv] = inc;
     __syncthreads();
-    uint32_t ex = glb(part)[blockIdx.x] + inc - s;
-    for (int q = 0; q < wv; ++q) ex += s_w[q];
-#pragma unroll
-    for (int e = 0; e < SC_PER; ++e) {
-        if (i0 + e < L) glb(out)[i0 + e] = ex;
-        ex += v[e];
+    uint32_t start = inc - t;
+    for (int q = 0; q < wv; ++q) start += s_w[q];
+    const int64_t b0 = (int64_t)blockIdx.x * CH;
+    uint32_t run = start + glb(part)[(int64_t)blockIdx.x * 256 + d];
+    for (int64_t b = b0; b < min(b0 + CH, NB); ++b) {
+        glb(off)[b * 256 + d] = run;
+        run += glb(cnt)[b * 256 + d];
     }
 }
 
@@ -204,7 +227,7 @@ __global__ __launch_bounds__(RS_TPB) void k_rs_down(const uint64_t* kin, const u
     const int64_t b = blockIdx.x, base = b * RS_TILE;
     const int c = (int)min((int64_t)RS_TILE, n - base);
     for (int q = tid; q < RS_WAVES * 256; q += RS_TPB) (&s_wc[0][0])[q] = 0;
-    if (tid < 256) s_goff[tid] = glb(off)[(int64_t)tid * NB + b];
+    if (tid < 256) s_goff[tid] = glb(off)[b * 256 + tid];
     __syncthreads();
     uint64_t key[RS_IPT];
     uint32_t val[RS_IPT], rk[RS_IPT];
@@ -216,13 +239,13 @@ __global__ __launch_bounds__(RS_TPB) void k_rs_down(const uint64_t* kin, const u
         const bool valid = p < c;
         key[r] = valid ? glb(kin)[base + p] : ~0ull;
         val[r] = valid ? glb(vin)[base + p] : 0u;
-        const uint32_t dg = (uint32_t)(key[r] >> sh) & 255u;
-        uint64_t peers = __ballot(valid);
+    }
 #pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const uint64_t bb = __ballot((dg >> bit) & 1u);
-            peers &= ((dg >> bit) & 1u) ? bb : ~bb;
-        }
+    for (int r = 0; r < RS_IPT; ++r) {
+        const int p = wv * RS_WITEMS + r * 64 + lane;
+        const bool valid = p < c;
+        const uint32_t dg = (uint32_t)(key[r] >> sh) & 255u;
+        const uint64_t peers = digit_peers(dg, valid);
         const uint32_t below = (uint32_t)__popcll(peers & lt);
         // every peer reads the count before its lowest lane writes the new
         // one (one wave: its LDS accesses run in program order)
@@ -284,18 +307,11 @@ __global__ __launch_bounds__(RS_TPB) void k_rs_down(const uint64_t* kin, const u
 // every thread finds the same runs; the thread of a run's first item copies
 // the run's keys to the same positions of the idle key buffer and sorts them
 // there together with the run's indices (runs are disjoint).
-__global__ __launch_bounds__(256) void k_rs_fix(const uint64_t* keys, uint64_t* scratch, uint32_t* vals,
-                                                int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const WRS_GLOBAL uint64_t* K = glb(keys);
-    WRS_GLOBAL uint64_t* S = glb(scratch);
-    WRS_GLOBAL uint32_t* V = glb(vals);
-    const uint64_t k = K[i];
-    const uint64_t top = k >> RS_LOW;
-    if ((k >> 52) >= 0x7FFull) return;  // +inf (or NaN on rejected input): nothing to order
-    if (i > 0 && (K[i - 1] >> RS_LOW) == top) return;
-    if (i + 1 >= n || (K[i + 1] >> RS_LOW) != top) return;
+constexpr int FIX_IPT = 8;  // items per thread of the fix-up (enough loads in flight per wave)
+
+__device__ void sort_run(const WRS_GLOBAL uint64_t* K, WRS_GLOBAL uint64_t* S, WRS_GLOBAL uint32_t* V, int64_t i,
+                         int64_t n) {
+    const uint64_t top = K[i] >> RS_LOW;
     int64_t e = i + 2;
     while (e < n && (K[e] >> RS_LOW) == top) ++e;
     for (int64_t a = i; a < e; ++a) S[a] = K[a];
@@ -313,12 +329,53 @@ __global__ __launch_bounds__(256) void k_rs_fix(const uint64_t* keys, uint64_t* 
     }
 }
 
+__global__ __launch_bounds__(256) void k_rs_fix(const uint64_t* keys, uint64_t* scratch, uint32_t* vals,
+                                                int64_t n) {
+    const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * FIX_IPT;
+    if (i0 >= n) return;
+    const WRS_GLOBAL uint64_t* K = glb(keys);
+    uint64_t k[FIX_IPT + 2];  // items i0 - 1 .. i0 + FIX_IPT
+    if (i0 + FIX_IPT <= n) {  // whole run of items: four 16-byte loads (i0 is a multiple of 8)
+#pragma unroll
+        for (int q = 0; q < FIX_IPT / 2; ++q) {
+            const vuint4 x = *(const WRS_GLOBAL vuint4*)(K + i0 + 2 * q);
+            k[1 + 2 * q] = ((uint64_t)x.y << 32) | x.x;
+            k[2 + 2 * q] = ((uint64_t)x.w << 32) | x.z;
+        }
+    } else {
+#pragma unroll
+        for (int e = 1; e <= FIX_IPT; ++e) k[e] = (i0 - 1 + e < n) ? K[i0 - 1 + e] : ~0ull;
+    }
+    k[0] = (i0 > 0) ? K[i0 - 1] : ~0ull;
+    k[FIX_IPT + 1] = (i0 + FIX_IPT < n) ? K[i0 + FIX_IPT] : ~0ull;
+#pragma unroll
+    for (int e = 1; e <= FIX_IPT; ++e) {
+        const int64_t i = i0 - 1 + e;
+        if (i >= n) break;
+        const uint64_t top = k[e] >> RS_LOW;
+        if ((k[e] >> 52) >= 0x7FFull) continue;  // +inf (or NaN on rejected input): nothing to order
+        if (i > 0 && (k[e - 1] >> RS_LOW) == top) continue;
+        if (i + 1 >= n || (k[e + 1] >> RS_LOW) != top) continue;
+        if (e + 1 <= FIX_IPT && (i + 2 >= n || (k[e + 2] >> RS_LOW) != top)) {
+            // a run of two (the common case), in registers: its indices are in
+            // index order, so they swap only when the keys are out of order
+            if (k[e] > k[e + 1]) {
+                WRS_GLOBAL uint32_t* V = glb(vals);
+                const uint32_t a = V[i], b = V[i + 1];
+                V[i] = b;
+                V[i + 1] = a;
+            }
+            continue;
+        }
+        sort_run(K, glb(scratch), glb(vals), i, n);
+    }
+}
+
 int launch_perm(const float* d_w, int64_t n, uint64_t seed, uint32_t sid, int32_t* d_out, void* ws,
                 hipStream_t st) {
     const PermLayout P = perm_layout(ws, n);
     const int64_t NB = cdiv(n, RS_TILE);
-    const int64_t L = 256 * NB;
-    const int64_t parts = cdiv(L, SC_PART);
+    const int64_t NC = cdiv(NB, CH);
 #define WRS_CHECK()                                      \
     do {                                                 \
         hipError_t e_ = hipGetLastError();               \
@@ -336,15 +393,14 @@ int launch_perm(const float* d_w, int64_t n, uint64_t seed, uint32_t sid, int32_
         const bool last = pass == RS_PASSES - 1;
         uint64_t* kout = (kin == P.kA) ? P.kB : P.kA;
         uint32_t* vout = last ? (uint32_t*)d_out : ((vin == P.vA) ? P.vB : P.vA);
-        hipLaunchKernelGGL(k_rs_up, dim3((unsigned)NB), dim3(RS_TPB), 0, st, (const uint64_t*)kin, n, sh, P.cnt, NB);
+        hipLaunchKernelGGL(k_rs_up, dim3((unsigned)NB), dim3(UP_TPB), 0, st, (const uint64_t*)kin, n, sh, P.cnt, NB);
         WRS_CHECK();
-        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)parts), dim3(SC_TPB), 0, st, (const uint32_t*)P.cnt, L,
-                           P.part);
+        hipLaunchKernelGGL(k_col_part, dim3((unsigned)NC), dim3(256), 0, st, (const uint32_t*)P.cnt, NB, P.part);
         WRS_CHECK();
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, P.part, parts);
+        hipLaunchKernelGGL(k_col_scan, dim3(256), dim3(256), 0, st, P.part, NC, P.tot);
         WRS_CHECK();
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)parts), dim3(SC_TPB), 0, st, (const uint32_t*)P.cnt, P.off,
-                           L, (const uint32_t*)P.part);
+        hipLaunchKernelGGL(k_col_apply, dim3((unsigned)NC), dim3(256), 0, st, (const uint32_t*)P.cnt,
+                           (const uint32_t*)P.part, (const uint32_t*)P.tot, NB, P.off);
         WRS_CHECK();
         hipLaunchKernelGGL(k_rs_down, dim3((unsigned)NB), dim3(RS_TPB), 0, st, (const uint64_t*)kin,
                            (const uint32_t*)vin, kout, vout, (const uint32_t*)P.off, n, sh, NB);
@@ -353,7 +409,7 @@ int launch_perm(const float* d_w, int64_t n, uint64_t seed, uint32_t sid, int32_
         vin = vout;
     }
     uint64_t* idle = (kin == P.kA) ? P.kB : P.kA;
-    hipLaunchKernelGGL(k_rs_fix, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, (const uint64_t*)kin, idle,
+    hipLaunchKernelGGL(k_rs_fix, dim3((unsigned)cdiv(n, 256 * FIX_IPT)), dim3(256), 0, st, (const uint64_t*)kin, idle,
                        (uint32_t*)d_out, n);
     WRS_CHECK();
 #undef WRS_CHECK
