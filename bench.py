@@ -137,6 +137,7 @@ def main():
         for fam in inputs:
             wrs.alias_build_plus(inputs[fam], n, table, pws)
         del pws
+        bench_perm(wrs, torch, np, workloads, reps=1)
         bench_wor(wrs, torch, np, workloads, reps=1)
         torch.cuda.synchronize()
         log(f"profile run done: build {tot_build / steps / 2:.3f} ms, sample {tot_sample / steps / 2:.3f} ms")
@@ -186,6 +187,7 @@ def main():
     if not args.skip_extras:
         result["build_plus"] = bench_plus(wrs, torch, inputs, n, table)
         result["without_replacement"] = bench_wor(wrs, torch, np, workloads)
+        result["permutation"] = bench_perm(wrs, torch, np, workloads)
         result["batched"] = bench_batched(wrs, torch, np, workloads, not args.no_tune)
         result["served"] = bench_served(wrs, torch, np, workloads)
         result["cpu_baseline"] = bench_cpu(np, workloads)
@@ -247,6 +249,32 @@ def bench_wor(wrs, torch, np, workloads, reps=5):
                             "hbm_frac_4B_per_item": round(4.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del out, ws
     return res
+
+
+def bench_perm(wrs, torch, np, workloads, reps=5):
+    """Weighted permutation (problem WRP) of the without-replacement input:
+    n = 2^26, power law s = 0.5 permuted (seed 3), Philox key 3.  Algorithmic
+    bytes: keys (4 B read, 12 B written), five radix passes of 32 B (8 B counted,
+    12 B read and 12 B written), 8 B read by the last pass over runs."""
+    dev = torch.device("cuda:0")
+    n = 1 << 26
+    log("permutation: n=2^26")
+    w = torch.from_numpy(workloads.power_law(n, 0.5, 3)).to(dev)
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = wrs.new_workspace(wrs.OP_PERM, n, 0, dev)
+    wrs.permutation(w, n, 3, 0, out, ws)
+    assert wrs.status(ws) == wrs.OK
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        wrs.permutation(w, n, 3, 0, out, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    alg = (16 + 5 * 32 + 8) * n
+    return {"workload": "n=2^26 FP32 weights, power law s=0.5 permuted (seed 3), Philox key 3",
+            "ms": round(ms, 4), "gitems_s": round(n / (ms * 1e-3) / 1e9, 2),
+            "hbm_frac_184B_per_item": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def tune(wrs, build_ns, sample_nks, run):
