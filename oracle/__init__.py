@@ -60,6 +60,9 @@ def _load():
         "orc_wor_keys_at": (ctypes.c_int, [P, i64, u64, u32, P, i64, P]),
         "orc_sample_wor": (ctypes.c_int, [P, i64, i64, u64, u32, P, P]),
         "orc_permutation": (ctypes.c_int, [P, i64, u64, u32, P]),
+        "orc_twolevel_build": (ctypes.c_int, [P, i64, i64, P, P, P, P]),
+        "orc_twolevel_sample": (ctypes.c_int, [P, P, P, P, i64, i64, u64, u32, u64, i64, P]),
+        "orc_twolevel_sample_at": (ctypes.c_int, [P, P, P, P, i64, i64, u64, u32, P, i64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -215,4 +218,39 @@ def permutation(w, seed, stream_id):
     w = _f32(w)
     out = np.empty(w.size, np.int32)
     _check("orc_permutation", _load().orc_permutation(_ptr(w), w.size, seed, stream_id, _ptr(out)))
+    return out
+
+
+def twolevel_build(w, block):
+    """Section 4.4, replicated top level: per-block alias tables (the sweep on
+    each block of `block` items, global alias indices) and a top-level table
+    over the block sums -> (t_top, a_top, t, alias)."""
+    w = _f32(w)
+    G = (w.size + block - 1) // block
+    tt = np.empty(G, np.float32)
+    at = np.empty(G, np.int32)
+    t = np.empty(w.size, np.float32)
+    a = np.empty(w.size, np.int32)
+    _check("orc_twolevel_build", _load().orc_twolevel_build(_ptr(w), w.size, int(block), _ptr(tt), _ptr(at),
+                                                            _ptr(t), _ptr(a)))
+    return tt, at, t, a
+
+
+def twolevel_sample(t_top, a_top, t, alias, block, seed, stream_id, first_counter, k):
+    args = [np.ascontiguousarray(x, d) for x, d in ((t_top, np.float32), (a_top, np.int32), (t, np.float32),
+                                                    (alias, np.int32))]
+    out = np.empty(k, np.int32)
+    _check("orc_twolevel_sample", _load().orc_twolevel_sample(*[_ptr(x) for x in args], args[2].size, int(block),
+                                                              seed, stream_id, first_counter, k, _ptr(out)))
+    return out
+
+
+def twolevel_sample_at(t_top, a_top, t, alias, block, seed, stream_id, counters):
+    args = [np.ascontiguousarray(x, d) for x, d in ((t_top, np.float32), (a_top, np.int32), (t, np.float32),
+                                                    (alias, np.int32))]
+    c = np.ascontiguousarray(counters, dtype=np.uint64)
+    out = np.empty(c.size, np.int32)
+    _check("orc_twolevel_sample_at", _load().orc_twolevel_sample_at(*[_ptr(x) for x in args], args[2].size,
+                                                                    int(block), seed, stream_id, _ptr(c), c.size,
+                                                                    _ptr(out)))
     return out

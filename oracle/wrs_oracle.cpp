@@ -21,6 +21,9 @@
  *                       Section 4.2 (Algorithm 3) produces exactly this table.
  *   orc_psaplus_build   greedy assignment inside blocks, then the sweep over the
  *                       items left (Section 4.2.1, PSA+), in exact arithmetic.
+ *   orc_twolevel_*      2-level alias table (Section 4.4, replicated top level):
+ *                       block tables by the sweep, a top table over the block
+ *                       sums, and its two-step query.
  *   orc_alias_sample*   alias queries (Section 2.2, last paragraph; branchless
  *                       select of Section 10), one Philox call per draw.
  *   orc_reconstruct     per-item mass implied by a table (alias-table definition,
@@ -513,6 +516,89 @@ extern "C" int orc_psaplus_build(const float* w, int64_t n, int64_t block, float
         }
     }
     sweep_list(left_idx, left_size, &W, t, alias);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 4.4 (replicated top level): a 2-level alias table.  The items are  */
+/* cut into consecutive blocks of `block` items; block b is a meta-item of    */
+/* weight W_b (the sum of its weights).  Each block gets its own alias table  */
+/* over its items (the sweep of Algorithm 2 with the block as the instance),  */
+/* stored in place in t/alias with global item indices; the top-level table   */
+/* over the meta-items is the sweep over the W_b, in exact arithmetic.        */
+/* Reading: a block of total weight 0 keeps (t = 1, alias = self) in every    */
+/* bucket; its meta-item has weight 0 and is never drawn.                     */
+/* ------------------------------------------------------------------------- */
+extern "C" int orc_twolevel_build(const float* w, int64_t n, int64_t block, float* t_top, int32_t* a_top,
+                                  float* t, int32_t* alias) {
+    if (!w || !t || !alias || !t_top || !a_top || n < 1 || n > 2147483647LL || block < 1) return ORC_EINVAL;
+    if (!valid_weights(w, n)) return ORC_EDOMAIN;
+    xnum W;
+    exact_sum(w, n, &W);
+    if (x_is_zero(&W)) return ORC_EDOMAIN;
+    const int64_t G = (n + block - 1) / block;
+    std::vector<int64_t> meta_idx((size_t)G);
+    std::vector<xnum> meta_size((size_t)G);
+    for (int64_t b = 0; b < G; ++b) {
+        const int64_t b0 = b * block, b1 = std::min(n, b0 + block);
+        xnum Wb;
+        x_zero(&Wb);
+        for (int64_t i = b0; i < b1; ++i) x_add_float_times(&Wb, w[i], 1u);
+        if (x_is_zero(&Wb)) {
+            for (int64_t i = b0; i < b1; ++i) { t[i] = 1.0f; alias[i] = (int32_t)i; }
+        } else {
+            int rc = orc_sweep_build(w + b0, b1 - b0, t + b0, alias + b0);
+            if (rc) return rc;
+            for (int64_t i = b0; i < b1; ++i) alias[i] += (int32_t)b0;
+        }
+        /* the meta-item's G-scaled size G * W_b, against the bucket W */
+        meta_idx[b] = b;
+        x_zero(&meta_size[b]);
+        for (int64_t i = b0; i < b1; ++i) x_add_float_times(&meta_size[b], w[i], (uint32_t)G);
+    }
+    sweep_list(meta_idx, meta_size, &W, t_top, a_top);
+    return ORC_OK;
+}
+
+/* Draws from a 2-level table: a top-level alias query picks the block g
+   (Philox block (s lo, s hi, stream_id, 0), the mapping of orc_alias_sample
+   over the G meta buckets), then an alias query inside block g picks the item
+   (Philox block (s lo, s hi, stream_id, 2), the same mapping over the block's
+   m items; its table entries hold global indices).  s = first_counter + j. */
+static inline int32_t twolevel_query(const float* t_top, const int32_t* a_top, const float* t,
+                                     const int32_t* alias, int64_t n, int64_t block, uint64_t seed,
+                                     uint32_t stream_id, uint64_t s) {
+    const int64_t G = (n + block - 1) / block;
+    uint32_t x[4];
+    philox_at(seed, s, stream_id, 0u, x);
+    uint64_t hi64 = ((uint64_t)x[1] << 32) | x[0];
+    int64_t r = (int64_t)(((unsigned __int128)hi64 * (uint64_t)G) >> 64);
+    float u = (float)(x[2] >> 8) * (1.0f / 16777216.0f);
+    const int64_t g = (u < t_top[r]) ? r : a_top[r];
+    const int64_t b0 = g * block, m = std::min(n, b0 + block) - b0;
+    philox_at(seed, s, stream_id, 2u, x);
+    hi64 = ((uint64_t)x[1] << 32) | x[0];
+    r = (int64_t)(((unsigned __int128)hi64 * (uint64_t)m) >> 64);
+    u = (float)(x[2] >> 8) * (1.0f / 16777216.0f);
+    return (u < t[b0 + r]) ? (int32_t)(b0 + r) : alias[b0 + r];
+}
+
+extern "C" int orc_twolevel_sample(const float* t_top, const int32_t* a_top, const float* t, const int32_t* alias,
+                                   int64_t n, int64_t block, uint64_t seed, uint32_t stream_id,
+                                   uint64_t first_counter, int64_t k, int32_t* out) {
+    if (!t_top || !a_top || !t || !alias || n < 1 || block < 1 || k < 0 || (k > 0 && !out)) return ORC_EINVAL;
+    for (int64_t j = 0; j < k; ++j)
+        out[j] = twolevel_query(t_top, a_top, t, alias, n, block, seed, stream_id, first_counter + (uint64_t)j);
+    return ORC_OK;
+}
+
+extern "C" int orc_twolevel_sample_at(const float* t_top, const int32_t* a_top, const float* t,
+                                      const int32_t* alias, int64_t n, int64_t block, uint64_t seed,
+                                      uint32_t stream_id, const uint64_t* counters, int64_t m, int32_t* out) {
+    if (!t_top || !a_top || !t || !alias || !counters || n < 1 || block < 1 || m < 0 || (m > 0 && !out))
+        return ORC_EINVAL;
+    for (int64_t j = 0; j < m; ++j)
+        out[j] = twolevel_query(t_top, a_top, t, alias, n, block, seed, stream_id, counters[j]);
     return ORC_OK;
 }
 
