@@ -53,15 +53,19 @@ enum {
     WRS_ENOTFOUND = -6  /* server: unknown table or request id */
 };
 
-enum { WRS_OP_BUILD = 1, WRS_OP_WOR = 2, WRS_OP_BUILD_PLUS = 3, WRS_OP_PERM = 4 };
+enum { WRS_OP_BUILD = 1, WRS_OP_WOR = 2, WRS_OP_BUILD_PLUS = 3, WRS_OP_PERM = 4, WRS_OP_TWOLEVEL = 5 };
+
+/* Items per block (meta-item) of the 2-level tables (part of their layout). */
+#define WRS_TWOLEVEL_BLOCK 2048
 
 /* Items per greedy block of wrs_alias_build_plus (part of its result). */
 #define WRS_PSAPLUS_BLOCK 2048
 
 /* Bytes of device workspace needed by wrs_alias_build (op = WRS_OP_BUILD, k
  * ignored), wrs_alias_build_plus (op = WRS_OP_BUILD_PLUS, k ignored),
- * wrs_sample_wor (op = WRS_OP_WOR) or wrs_permutation (op = WRS_OP_PERM, k
- * ignored).  Depends on n (and k) only.
+ * wrs_sample_wor (op = WRS_OP_WOR), wrs_permutation (op = WRS_OP_PERM, k
+ * ignored) or wrs_twolevel_build (op = WRS_OP_TWOLEVEL, k ignored).  Depends
+ * on n (and k) only.
  * Returns 0 for invalid arguments. */
 size_t wrs_workspace_bytes(int op, int64_t n, int64_t k);
 
@@ -109,6 +113,29 @@ int wrs_alias_build_plus(const float* d_w, int64_t n, wrs_entry* d_table,
  * d_out is then unspecified. */
 int wrs_permutation(const float* d_w, int64_t n, uint64_t seed, uint32_t stream_id, int32_t* d_out,
                     void* d_ws, size_t ws_bytes, void* stream);
+
+/* Build a 2-level alias table (Section 4.4, replicated top level).  The items
+ * are cut into blocks of WRS_TWOLEVEL_BLOCK consecutive items; block g is a
+ * meta-item whose weight is the sum of its items' weights.  d_table[0..n)
+ * receives every block's own alias table (the sweep of Section 4.1 with the
+ * block as the instance; aliases are global item indices), and
+ * d_top[0..G), G = ceil(n / WRS_TWOLEVEL_BLOCK), the alias table over the
+ * meta-items (the splitting construction of wrs_alias_build).  A block of
+ * total weight 0 keeps t = 1, alias = self and is never drawn.  d_w: n FP32
+ * weights (device).  d_table, d_top: device, 8-byte aligned.  d_ws:
+ * wrs_workspace_bytes(WRS_OP_TWOLEVEL, n, 0) bytes (device, 256-byte aligned,
+ * about 0.1 byte per item plus a fixed part).  Stream-ordered, no host wait
+ * (graph-capturable).  Domain errors go to the workspace status word. */
+int wrs_twolevel_build(const float* d_w, int64_t n, wrs_entry* d_table, wrs_entry* d_top,
+                       void* d_ws, size_t ws_bytes, void* stream);
+
+/* k draws from a 2-level table: draw s (counter c = first_counter + s) picks
+ * block g by the query of wrs_alias_sample over the G top-level buckets with
+ * Philox counter (c lo, c hi, stream_id, 0), then the item by the same query
+ * over the block's m items with Philox counter (c lo, c hi, stream_id, 2).
+ * Each draw reads the top table (small: L2-resident) and one block entry. */
+int wrs_twolevel_sample(const wrs_entry* d_top, const wrs_entry* d_table, int64_t n, uint64_t seed,
+                        uint32_t stream_id, uint64_t first_counter, int64_t k, int32_t* d_out, void* stream);
 
 /* After wrs_alias_build_plus on this workspace: the number of items its
  * greedy blocks left to the splitting stage (0 if the weights were rejected).

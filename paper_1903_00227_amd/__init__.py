@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwrs.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EDEVICE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-OP_BUILD, OP_WOR, OP_BUILD_PLUS, OP_PERM = 1, 2, 3, 4
+OP_BUILD, OP_WOR, OP_BUILD_PLUS, OP_PERM, OP_TWOLEVEL = 1, 2, 3, 4, 5
+TWOLEVEL_BLOCK = 2048  # items per block (meta-item) of the 2-level tables
 PSAPLUS_BLOCK = 2048  # items per greedy block of alias_build_plus
 TUNE_BUILD, TUNE_SAMPLE = 1, 2
 
@@ -57,6 +58,11 @@ EXPORTS = {
                                             ctypes.c_size_t, ctypes.c_void_p]),
     "wrs_permutation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "wrs_twolevel_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "wrs_twolevel_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
+                                           ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
     "wrs_plus_leftovers": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "wrs_alias_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
                                         ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
@@ -177,6 +183,16 @@ def alias_build_plus(w, n, table, ws, stream=None):
 def permutation(w, n, seed, stream_id, out, ws, stream=None):
     """Weighted random permutation of the n items into out (int32)."""
     _check("wrs_permutation", lib().wrs_permutation(_ptr(w), n, seed, stream_id, _ptr(out), _ptr(ws), ws.numel() if hasattr(ws, "numel") else ws_bytes_of(ws), _stream(stream)))
+
+
+def twolevel_build(w, n, table, top, ws, stream=None):
+    """2-level alias table: block tables into table (n entries), top table over
+    the blocks into top (ceil(n / 2048) entries)."""
+    _check("wrs_twolevel_build", lib().wrs_twolevel_build(_ptr(w), n, _ptr(table), _ptr(top), _ptr(ws), ws.numel() if hasattr(ws, "numel") else ws_bytes_of(ws), _stream(stream)))
+
+
+def twolevel_sample(top, table, n, seed, stream_id, first_counter, k, out, stream=None):
+    _check("wrs_twolevel_sample", lib().wrs_twolevel_sample(_ptr(top), _ptr(table), n, seed, stream_id, first_counter, k, _ptr(out), _stream(stream)))
 
 
 def plus_leftovers(ws, stream=None) -> int:

@@ -40,6 +40,7 @@ extern "C" size_t wrs_workspace_bytes(int op, int64_t n, int64_t k) {
     if (op == WRS_OP_BUILD) return build_ws_bytes(n);
     if (op == WRS_OP_BUILD_PLUS) return plus_ws_bytes(n);
     if (op == WRS_OP_PERM) return perm_ws_bytes(n);
+    if (op == WRS_OP_TWOLEVEL) return twolevel_ws_bytes(n);
     if (op == WRS_OP_WOR) return wor_ws_bytes(n, k);
     return 0;
 }
@@ -122,6 +123,57 @@ extern "C" int wrs_permutation(const float* d_w, int64_t n, uint64_t seed, uint3
     if (((uintptr_t)d_out) & 3) { set_error("wrs_permutation: output not 4-byte aligned"); return WRS_EINVAL; }
     const int e = launch_perm(d_w, n, seed, stream_id, d_out, d_ws, (hipStream_t)stream);
     if (e != 0) return dev_fail("wrs_permutation launch", (hipError_t)e);
+    return WRS_OK;
+}
+
+extern "C" int wrs_twolevel_build(const float* d_w, int64_t n, wrs_entry* d_table, wrs_entry* d_top, void* d_ws,
+                                  size_t ws_bytes, void* stream) {
+    g_err[0] = 0;
+    if (!d_w || !d_table || !d_top || !d_ws) { set_error("wrs_twolevel_build: null pointer"); return WRS_EINVAL; }
+    if (n < 1 || n > N_MAX) { set_error("wrs_twolevel_build: n = %lld out of [1, 2^31-1]", (long long)n); return WRS_EINVAL; }
+    if (ws_bytes < twolevel_ws_bytes(n)) { set_error("wrs_twolevel_build: workspace %zu < %zu bytes", ws_bytes, twolevel_ws_bytes(n)); return WRS_EINVAL; }
+    if (((uintptr_t)d_ws) & 255) { set_error("wrs_twolevel_build: workspace not 256-byte aligned"); return WRS_EINVAL; }
+    if ((((uintptr_t)d_table) | ((uintptr_t)d_top)) & 7) { set_error("wrs_twolevel_build: tables not 8-byte aligned"); return WRS_EINVAL; }
+    const hipStream_t st = (hipStream_t)stream;
+    JobTable jt;
+    memset(&jt, 0, sizeof jt);
+    JobTable jtop;
+    memset(&jtop, 0, sizeof jtop);
+    TwoLayout T;
+    JobDesc& J = jt.one;
+    JobDesc& L = jtop.one;
+    twolevel_layout(d_ws, n, J, L, T);
+    J.w = d_w;
+    J.table = d_table;
+    L.table = d_top;
+    // total weight and grid (the reduction phases of the main job)
+    int64_t blocks[PH_COUNT];
+    phase_blocks(J, blocks);
+    for (int p = PH_TILE; p < PH_COUNT; ++p) blocks[p] = 0;
+    hipError_t e = launch_build(jt, blocks, st);
+    // the top job's scalars (n = G meta-items) on the items' grid: its sizes,
+    // G times the blocks' exact sums, are integers of that grid
+    if (e == hipSuccess) e = launch_finalize_on_grid(L, J.sc, st);
+    // block tables and meta-items, then the top table (list mode)
+    if (e == hipSuccess) e = launch_twolvl(J, T, st);
+    if (e == hipSuccess) {
+        phase_blocks(L, blocks);
+        e = launch_build(jtop, blocks, st, true);
+    }
+    if (e != hipSuccess) return dev_fail("wrs_twolevel_build launch", e);
+    return WRS_OK;
+}
+
+extern "C" int wrs_twolevel_sample(const wrs_entry* d_top, const wrs_entry* d_table, int64_t n, uint64_t seed,
+                                   uint32_t stream_id, uint64_t first_counter, int64_t k, int32_t* d_out,
+                                   void* stream) {
+    g_err[0] = 0;
+    if (!d_top || !d_table || (k > 0 && !d_out)) { set_error("wrs_twolevel_sample: null pointer"); return WRS_EINVAL; }
+    if (n < 1 || n > N_MAX || k < 0) { set_error("wrs_twolevel_sample: bad n or k"); return WRS_EINVAL; }
+    if (cdiv(k, 256 * 4) > 0x7fffffffLL) { set_error("wrs_twolevel_sample: k too large"); return WRS_EINVAL; }
+    if ((((uintptr_t)d_table) | ((uintptr_t)d_top)) & 7) { set_error("wrs_twolevel_sample: tables not 8-byte aligned"); return WRS_EINVAL; }
+    const hipError_t e = launch_sample2(d_top, d_table, n, seed, stream_id, first_counter, k, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail("wrs_twolevel_sample launch", e);
     return WRS_OK;
 }
 

@@ -30,6 +30,7 @@
 #include <float.h>
 #include <math.h>
 #include <stdio.h>
+#include <string.h>
 
 #include "wrs_device.h"
 
@@ -140,6 +141,46 @@ static PlusOffsets plus_offsets(int64_t n) {
 
 size_t plus_ws_bytes(int64_t n) { return plus_offsets(n).total; }
 
+// 2-level workspace: the main job's scalars and reduction partials (the head of
+// its build layout), the top job's build workspace, then the meta-item lists.
+struct TwoOffsets {
+    size_t top, lidx, lw, lres, PI, total;
+};
+
+static TwoOffsets two_offsets(int64_t n) {
+    const int64_t G = cdiv(n, GTILE);
+    const int64_t Ct = cdiv(G, TILE);
+    TwoOffsets o;
+    size_t p = align256(layout_for(n).NL);
+    o.top = p;  p = align256(p + layout_for(G).total);
+    o.lidx = p; p = align256(p + sizeof(uint32_t) * Ct * TILE);
+    o.lw = p;   p = align256(p + sizeof(float) * Ct * TILE);
+    o.lres = p; p = align256(p + sizeof(u128) * G);
+    o.PI = p;   p = align256(p + sizeof(uint32_t) * Ct * TILE);
+    o.total = p;
+    return o;
+}
+
+size_t twolevel_ws_bytes(int64_t n) { return two_offsets(n).total; }
+
+void twolevel_layout(void* ws, int64_t n, JobDesc& J, JobDesc& top, TwoLayout& T) {
+    const TwoOffsets o = two_offsets(n);
+    const int64_t G = cdiv(n, GTILE);
+    char* b = (char*)ws;
+    build_ws_layout(J, ws, n);  // only sc, red and redinfo are used (the head)
+    build_ws_layout(top, b + o.top, G);
+    T.lidx = (uint32_t*)(b + o.lidx);
+    T.lw = (float*)(b + o.lw);
+    T.lres = (u128*)(b + o.lres);
+    T.PI = (uint32_t*)(b + o.PI);
+    top.w = T.lw;
+    top.lidx = T.lidx;
+    top.lres = T.lres;
+    top.PI = T.PI;
+    top.nmul = (uint32_t)G;
+    build_list_layout(top, G);
+}
+
 PlusLayout plus_layout(void* ws, int64_t n) {
     const PlusOffsets o = plus_offsets(n);
     char* b = (char*)ws;
@@ -244,6 +285,46 @@ __device__ __forceinline__ u128 u128_from_integral_double(double d) {
 // a1 (second half): combine partials in a fixed order, derive the grid.
 // Grid exponent G, integer capacity Q and the derived scalars, from the total
 // weight hi + lo (double-double) and the domain flags; one thread.
+// The scalars that depend on the item count n, given the grid exponent G and
+// the capacity Q (status OK).
+__device__ void derive_scalars(BuildScalars& S, int64_t n) {
+    const int G = S.G;
+    const u128 Q = S.Q;
+    S.Qd = u128_to_double(Q);
+    S.rQ = 1.0 / S.Qd;
+    S.nscale = ldexp((double)n, -G);
+    // floor(Q / n) without 128-bit division: estimate, then correct (the
+    // estimate is off by at most one or two; the loops are bounded anyway).
+    // A job over few meta-items on the items' grid can have Q / n >= 2^64:
+    // its items are markers with exact sizes, so Qn (the FP32 light test) is
+    // unused there and saturates.
+    uint64_t qn = ~0ull;
+    if ((uint64_t)(Q >> 64) < (uint64_t)n) {
+        qn = (uint64_t)fmin(S.Qd / (double)n, 18446744073709549568.0);  // largest double below 2^64
+        const i128 rem = (i128)Q - (i128)n * (i128)qn;
+        qn = (uint64_t)((i128)qn + rem / (i128)n);
+        for (int it = 0; it < 4 && (u128)n * (u128)(qn + 1) <= Q; ++it) ++qn;
+        for (int it = 0; it < 4 && (u128)n * (u128)qn > Q; ++it) --qn;
+    }
+    S.Qn = qn;
+    // merge keys: prefix sums (at most n Q) shifted right to fit 62 bits
+    const uint64_t qh = (uint64_t)(Q >> 64), ql = (uint64_t)Q;
+    const int qbits = qh ? 128 - __clzll((long long)qh) : 64 - __clzll((long long)ql);
+    const int nbits = 64 - __clzll((long long)n);
+    const int sh = max(0, qbits + nbits - 62);
+    S.kshift = sh;
+    S.tscale = ldexp(1.0, sh) * S.rQ;
+    S.Qk = (uint64_t)((Q + (sh > 0 ? ((u128)1 << (sh - 1)) : (u128)0)) >> sh);
+    // quantize is monotone in w and FP32 bit patterns of w >= 0 are ordered
+    // like the values: find the smallest pattern with q > Qn.
+    uint32_t lo = 0, hi = 0x7F800000u;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (quantize(__uint_as_float(mid), G) > (u128)qn) hi = mid; else lo = mid + 1;
+    }
+    S.wthr = lo;
+}
+
 __device__ void finalize_scalars(const JobDesc& J, double hi, double lo, uint32_t bad, uint32_t pos) {
     BuildScalars S;
     S.status = WRS_OK;
@@ -278,34 +359,24 @@ __device__ void finalize_scalars(const JobDesc& J, double hi, double lo, uint32_
         Q = (u128)((i128)Q + (i128)(int64_t)Ql);
         S.G = G;
         S.Q = Q;
-        S.Qd = u128_to_double(Q);
-        S.rQ = 1.0 / S.Qd;
-        S.nscale = ldexp((double)n, -G);
-        // floor(Q / n) without 128-bit division: estimate, then correct.
-        uint64_t qn = (uint64_t)(S.Qd / (double)n);
-        const i128 rem = (i128)Q - (i128)n * (i128)qn;
-        qn = (uint64_t)((int64_t)qn + (int64_t)(rem / (i128)n));
-        while ((u128)n * (u128)(qn + 1) <= Q) ++qn;
-        while ((u128)n * (u128)qn > Q) --qn;
-        S.Qn = qn;
-        // merge keys: prefix sums (at most n Q) shifted right to fit 62 bits
-        const uint64_t qh = (uint64_t)(Q >> 64), ql = (uint64_t)Q;
-        const int qbits = qh ? 128 - __clzll((long long)qh) : 64 - __clzll((long long)ql);
-        const int nbits = 64 - __clzll((long long)n);
-        const int sh = max(0, qbits + nbits - 62);
-        S.kshift = sh;
-        S.tscale = ldexp(1.0, sh) * S.rQ;
-        S.Qk = (uint64_t)((Q + (sh > 0 ? ((u128)1 << (sh - 1)) : (u128)0)) >> sh);
-        // quantize is monotone in w and FP32 bit patterns of w >= 0 are ordered
-        // like the values: find the smallest pattern with q > Qn.
-        uint32_t lo = 0, hi = 0x7F800000u;
-        while (lo < hi) {
-            const uint32_t mid = lo + ((hi - lo) >> 1);
-            if (quantize(__uint_as_float(mid), G) > (u128)qn) hi = mid; else lo = mid + 1;
-        }
-        S.wthr = lo;
+        derive_scalars(S, n);
     }
     *J.sc = S;
+}
+
+// Scalars of a job over m <= n meta-items on the grid of a finished job over
+// the n items (same G and Q, so its sizes are exact in the same integers).
+__global__ void k_finalize_on_grid(JobDesc top, const BuildScalars* base) {
+    if (threadIdx.x != 0) return;
+    BuildScalars S = *base;
+    S.nleft = 0;
+    if (S.status == WRS_OK) derive_scalars(S, top.n);
+    *top.sc = S;
+}
+
+hipError_t launch_finalize_on_grid(const JobDesc& top, const BuildScalars* base, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize_on_grid, dim3(1), dim3(64), 0, st, top, base);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(TPB) void k_finalize(JobTable jt) {

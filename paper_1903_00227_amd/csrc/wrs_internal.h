@@ -134,6 +134,19 @@ struct PlusLayout {
 };
 size_t plus_ws_bytes(int64_t n);
 PlusLayout plus_layout(void* ws, int64_t n);
+
+// 2-level tables: the main job (reduction only), the top-level list job over
+// the G = ceil(n / GTILE) meta-items, and the meta-items themselves.
+struct TwoLayout {
+    uint32_t* lidx;  // [C_top * TILE] list item g is meta-item g
+    float* lw;       // [C_top * TILE] residual markers
+    u128* lres;      // [G] exact G-scaled size of each meta-item
+    uint32_t* PI;    // [C_top * TILE] list-mode partitioned indices
+};
+size_t twolevel_ws_bytes(int64_t n);
+// J: main job over the n items; top: the list job over the meta-items (its
+// scalars are its own, finalized from J's reduction partials).
+void twolevel_layout(void* ws, int64_t n, JobDesc& J, JobDesc& top, TwoLayout& T);
 void set_sample_job(JobDesc& J, int64_t k, int32_t sunroll = 0);
 int64_t sample_blocks(const JobDesc& J);
 
@@ -153,6 +166,11 @@ hipError_t launch_build(const JobTable& jt, const int64_t* blocks, hipStream_t s
 // Greedy stage of PSA+ for one job (reduction already launched): greedy blocks,
 // prefix of their leftover counts (into sc->nleft), compaction.
 hipError_t launch_greedy(const JobDesc& J, const PlusLayout& P, hipStream_t st);
+// The scalars of a job over meta-items on the grid (G, Q) of a finished job.
+hipError_t launch_finalize_on_grid(const JobDesc& top, const BuildScalars* base, hipStream_t st);
+hipError_t launch_twolvl(const JobDesc& J, const TwoLayout& T, hipStream_t st);
+hipError_t launch_sample2(const wrs_entry* top, const wrs_entry* table, int64_t n, uint64_t seed, uint32_t sid,
+                          uint64_t first, int64_t k, int32_t* out, hipStream_t st);
 hipError_t launch_sample(const JobTable& jt, int64_t blocks, hipStream_t st);
 // jt.jobs[j].sc->status -> d_dst[j] for every job (device memory, jobs on the device)
 hipError_t launch_collect_status(const JobTable& jt, int32_t* d_dst, hipStream_t st);

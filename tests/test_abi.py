@@ -95,3 +95,19 @@ def test_permutation_host_validation(wrs):
     assert "workspace" in wrs.last_error()
     assert L.wrs_permutation(fake, n, 0, 0, fake, ctypes.c_void_p((1 << 20) + 16), nb, None) == wrs.EINVAL
     assert L.wrs_permutation(fake, n, 0, 0, ctypes.c_void_p((1 << 20) + 2), fake, nb, None) == wrs.EINVAL
+
+
+def test_twolevel_host_validation(wrs):
+    L = wrs.lib()
+    n = 1 << 20
+    nb = L.wrs_workspace_bytes(wrs.OP_TWOLEVEL, n, 0)
+    assert 0 < nb < n // 4 + (1 << 20)  # small: reduction partials, the top job, the meta-items
+    assert L.wrs_twolevel_build(None, n, None, None, None, 0, None) == wrs.EINVAL
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.wrs_twolevel_build(fake, n, fake, fake, fake, nb - 1, None) == wrs.EINVAL
+    assert "workspace" in wrs.last_error()
+    assert L.wrs_twolevel_build(fake, n, fake, ctypes.c_void_p((1 << 20) + 4), fake, nb, None) == wrs.EINVAL
+    assert L.wrs_twolevel_sample(None, fake, n, 0, 0, 0, 10, fake, None) == wrs.EINVAL
+    assert L.wrs_twolevel_sample(fake, fake, 0, 0, 0, 0, 10, fake, None) == wrs.EINVAL
+    assert L.wrs_twolevel_sample(fake, fake, n, 0, 0, 0, -1, fake, None) == wrs.EINVAL
+    assert wrs.TWOLEVEL_BLOCK == 2048
