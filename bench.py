@@ -137,6 +137,11 @@ def main():
         for fam in inputs:
             wrs.alias_build_plus(inputs[fam], n, table, pws)
         del pws
+        top = wrs.new_table(-(-n // 2048), dev)
+        tws = wrs.new_workspace(wrs.OP_TWOLEVEL, n, 0, dev)
+        for fam in inputs:
+            wrs.twolevel_build(inputs[fam], n, table, top, tws)
+        del top, tws
         bench_perm(wrs, torch, np, workloads, reps=1)
         bench_wor(wrs, torch, np, workloads, reps=1)
         torch.cuda.synchronize()
@@ -186,6 +191,7 @@ def main():
         result["roofline"]["traffic_frac"] = round(tgbs / HBM_PEAK_GBS, 4)
     if not args.skip_extras:
         result["build_plus"] = bench_plus(wrs, torch, inputs, n, table)
+        result["two_level"] = bench_twolevel(wrs, torch, inputs, n, table, k, out)
         result["without_replacement"] = bench_wor(wrs, torch, np, workloads)
         result["permutation"] = bench_perm(wrs, torch, np, workloads)
         result["batched"] = bench_batched(wrs, torch, np, workloads, not args.no_tune)
@@ -221,6 +227,37 @@ def bench_plus(wrs, torch, inputs, n, table, reps=5):
         res[fam] = {"ms": round(ms, 4), "wall_ms": round(wall_ms, 4), "gitems_s": round(n / (ms * 1e-3) / 1e9, 2),
                     "left_fraction": round(left / n, 4)}
     del ws
+    return res
+
+
+def bench_twolevel(wrs, torch, inputs, n, table, k, out, reps=5):
+    """2-level alias tables (Section 4.4, replicated top level; blocks of 2048
+    items) on the same resident inputs: build, and k draws by the two-step
+    query.  A different table layout from the headline's, with the same item
+    probabilities."""
+    dev = torch.device("cuda:0")
+    log("two-level tables")
+    top = wrs.new_table(-(-n // 2048), dev)
+    ws = wrs.new_workspace(wrs.OP_TWOLEVEL, n, 0, dev)
+    res = {"workload": "the same n=2^28 inputs and k=2^30 draws, 2-level table (blocks of 2048)"}
+    for fam, w in inputs.items():
+        wrs.twolevel_build(w, n, table, top, ws)
+        wrs.twolevel_sample(top, table, n, 2, 0, 0, k, out)
+        torch.cuda.synchronize()
+        assert wrs.status(ws) == wrs.OK
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            wrs.twolevel_build(w, n, table, top, ws)
+        e[1].record()
+        wrs.twolevel_sample(top, table, n, 2, 0, 0, k, out)
+        e[2].record()
+        torch.cuda.synchronize()
+        bms = e[0].elapsed_time(e[1]) / reps
+        sms = e[1].elapsed_time(e[2])
+        res[fam] = {"build_ms": round(bms, 4), "build_gitems_s": round(n / (bms * 1e-3) / 1e9, 2),
+                    "sample_ms": round(sms, 3), "sample_gsamples_s": round(k / (sms * 1e-3) / 1e9, 2)}
+    del top, ws
     return res
 
 
