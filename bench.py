@@ -459,6 +459,12 @@ def bench_served(wrs, torch, np, workloads, count=3000):
            "rate_per_s": round(rate, 1)}
     res["continuous_batching"] = run("batch", rate)
     res["one_launch_per_request"] = run("one", rate)
+    # Saturated: the whole trace submitted at once; completion throughput.
+    sat = run("batch", 1e9)
+    res["saturated"] = {"continuous_batching": {k: sat[k] for k in ("req_per_s", "gitems_plus_gsamples_s", "p50_us",
+                                                                  "p99_us", "launches")},
+                        "one_launch_per_request": {k: probe[k] for k in ("req_per_s", "gitems_plus_gsamples_s",
+                                                                         "p50_us", "p99_us", "launches")}}
     return res
 
 
