@@ -134,3 +134,23 @@ def test_build_full_size(wrs, orc, fam):
     light, tl = orc.light_t_at(w, idx)
     il = idx[light]
     assert np.all(ulp_diff(t[il], tl[light]) <= 1)
+
+
+def test_build_exact_instances_bit_identical(wrs, orc):
+    """Integer weights in [0, 2^10] with n up to 2^16 (exact-arithmetic
+    instances): every prefix sum is exact and every item size is an exact
+    multiple of the key unit, so the merge is the exact sweep's.  On these
+    fixed instances the whole table, thresholds included, is bit-identical to
+    the oracle's (the general bar for thresholds is 1 ulp: a light's t passes
+    through FP64 before its one FP32 rounding)."""
+    rng = np.random.default_rng(31)
+    for n in (1, 7, 1000, 1024, 1025, 4097, 65536):
+        w = rng.integers(0, 1025, n).astype(np.float32)
+        if w.sum() == 0:
+            w[0] = 1.0
+        say("exact instance", n)
+        t, a, st, *_ = gpu_build(wrs, w)
+        assert st == wrs.OK
+        t_ref, a_ref = orc.sweep_build(w)
+        assert np.array_equal(a, a_ref), n
+        assert np.array_equal(t.view(np.uint32), t_ref.view(np.uint32)), n
