@@ -11,7 +11,10 @@ oracle for exact values):
     1e-6 relative of w_i / W, and 2^20 draws equal the oracle's two-step query
     of the same tables;
   - permutation: every item exactly once, and at 2^16 sampled positions the
-    oracle keys of neighbouring items ascend (up to 1e-12 relative).
+    oracle keys of neighbouring items ascend (up to 1e-12 relative);
+  - sampling without replacement (k = 2^16): ascending distinct indices, 2^20
+    random unselected items all have oracle keys at or above the largest
+    selected key, and the selection is the permutation's first k items.
 """
 import numpy as np
 import pytest
@@ -153,3 +156,31 @@ def test_max_size_permutation(wrs, orc, weights):
     ka = orc.wor_keys_at(w_np, 6, 0, o[pos].astype(np.int64))
     kb = orc.wor_keys_at(w_np, 6, 0, o[pos + 1].astype(np.int64))
     assert np.all(kb >= ka * (1 - 1e-12))
+
+
+def test_max_size_wor(wrs, orc, weights):
+    import torch
+    w_np, _ = weights
+    dev = torch.device("cuda:0")
+    k = 1 << 16
+    w = torch.from_numpy(w_np).to(dev)
+    sel = torch.empty(k, dtype=torch.int32, device=dev)
+    ws = wrs.new_workspace(wrs.OP_WOR, N, k, dev)
+    say("max size: without replacement")
+    wrs.sample_wor(w, N, k, 6, 0, sel, ws)
+    assert wrs.status(ws) == wrs.OK
+    del ws
+    torch.cuda.empty_cache()
+    s = sel.cpu().numpy()
+    assert np.all(np.diff(s) > 0) and s[0] >= 0 and s[-1] < N
+    kappa = orc.wor_keys_at(w_np, 6, 0, s.astype(np.int64)).max()
+    rng = np.random.default_rng(12)
+    others = np.setdiff1d(rng.integers(0, N, 1 << 20), s)
+    assert np.all(orc.wor_keys_at(w_np, 6, 0, others.astype(np.int64)) >= kappa * (1 - 1e-6))
+    say("max size: without replacement against the permutation's prefix")
+    out = torch.empty(N, dtype=torch.int32, device=dev)
+    pws = wrs.new_workspace(wrs.OP_PERM, N, 0, dev)
+    wrs.permutation(w, N, 6, 0, out, pws)
+    assert wrs.status(pws) == wrs.OK
+    assert np.array_equal(np.sort(out[:k].cpu().numpy()), s)
+
