@@ -246,12 +246,23 @@ int wrs_tune_load(const char* path);
  * requests draw from them.  Admission is limited by an HBM budget; admitted
  * requests are packed into batched launches while earlier batches are still
  * running (continuous batching), or issued one launch per request in arrival
- * order when `one_at_a_time` is set (the baseline). */
+ * order when `one_at_a_time` is set (the baseline).
+ * wrs_serve_create reserves the whole budget as one device allocation and,
+ * per concurrent batch, descriptor buffers for max_batch requests (device
+ * memory from the budget and pinned host memory); requests allocate nothing
+ * outside the budget.  Idle tables are evicted, least recently used first, to
+ * admit a build.  A build that cannot be admitted while nothing runs and no
+ * table is idle (the budget is held by tables that requests queued behind it
+ * still need) fails with WRS_ENOMEM rather than wait for ever; so do draws
+ * from its table.  A batch whose launch fails fails all its requests with
+ * WRS_EDEVICE. */
+#define WRS_SERVE_MAX_BATCH 4096
+#define WRS_SERVE_MAX_INFLIGHT 16
 typedef struct {
-    size_t hbm_budget_bytes;   /* tables + per-request workspace, bytes */
-    int32_t max_batch;         /* requests per batched launch (>= 1) */
+    size_t hbm_budget_bytes;   /* tables + per-request workspace + descriptors, bytes (>= 1 MiB) */
+    int32_t max_batch;         /* requests per batched launch, 1..WRS_SERVE_MAX_BATCH */
     int32_t one_at_a_time;     /* 0: continuous batching, 1: one launch per request, FIFO */
-    int32_t inflight;          /* batches that may run concurrently (>= 1) */
+    int32_t inflight;          /* batches that may run concurrently, 1..WRS_SERVE_MAX_INFLIGHT */
 } wrs_serve_config;
 
 typedef struct {

@@ -3,7 +3,8 @@
 // Build requests create resident alias tables; sample requests draw from them.
 // A scheduler thread admits requests in arrival order while they fit an HBM
 // budget (one device pool carved by a first-fit allocator, so no hipMalloc on
-// the request path), packs admitted requests into batched launches (all builds
+// the request path; each slot's descriptor buffers, device and pinned host, are
+// reserved at creation), packs admitted requests into batched launches (all builds
 // of a tick share one launch per phase, all samples share one sampler launch),
 // and keeps up to `inflight` such batches running on separate streams while it
 // forms the next (continuous batching).  With one_at_a_time = 1 the same loop
@@ -120,7 +121,8 @@ struct Request {
 
 struct Batch {
     int slot;
-    hipEvent_t ev;
+    bool ok = true;  // false: a launch or copy of the batch failed (all its requests fail)
+    hipEvent_t ev = nullptr;
     std::vector<Request*> reqs;
     std::vector<std::pair<void*, size_t>> scratch;  // pool memory to give back
     const int32_t* h_status = nullptr;  // build statuses, copied to the slot's pinned buffer by the batch
@@ -136,9 +138,11 @@ struct Server {
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     std::unordered_map<uint64_t, std::unique_ptr<Table>> tables;
     std::vector<hipStream_t> streams;
-    std::vector<char*> staging;  // pinned host buffers for descriptors, one per slot
-    std::vector<size_t> staging_bytes;
+    std::vector<char*> staging;   // pinned host buffers for descriptors, one per slot
+    std::vector<char*> dev_desc;  // device descriptor buffers (pool memory), one per slot
     std::vector<bool> slot_busy;
+    int maxb = 1;         // requests per batch
+    size_t reserved = 0;  // pool bytes of the slots' descriptor buffers
     std::deque<Batch> running;
     std::thread worker;
     bool stop = false;
@@ -159,6 +163,10 @@ static size_t descriptor_bytes(int njobs) {
 
 static size_t status_bytes(int njobs) { return ((size_t)sizeof(int32_t) * njobs + 255) & ~(size_t)255; }
 
+// Descriptor bytes one slot needs for a batch of up to `maxb` requests: the
+// build and sample job tables (nb + ns <= maxb) and the build statuses.
+static size_t slot_bytes(int maxb) { return 2 * descriptor_bytes(maxb) + status_bytes(maxb); }
+
 static void finish_request(Server& S, Request* r, int status, double t) {
     r->status = status;
     r->done = true;
@@ -169,20 +177,22 @@ static void finish_request(Server& S, Request* r, int status, double t) {
     S.t_last = std::max(S.t_last, t);
     auto it = S.tables.find(r->table_id);
     if (it != S.tables.end()) it->second->refs--;
+    S.cv_done.notify_all();
 }
 
 // Retire finished batches (called with the lock held).
 static void retire(Server& S, bool block) {
     while (!S.running.empty()) {
         Batch& b = S.running.front();
-        hipError_t q = block ? hipEventSynchronize(b.ev) : hipEventQuery(b.ev);
+        // no event: it could not be created and the stream was synchronised
+        hipError_t q = !b.ev ? hipSuccess : block ? hipEventSynchronize(b.ev) : hipEventQuery(b.ev);
         if (q == hipErrorNotReady) break;
         const double t = now_s();
         // read build statuses from the device for the tables built in this batch
         for (Request* r : b.reqs) {
             auto it = S.tables.find(r->table_id);
             Table* tb = (it != S.tables.end()) ? it->second.get() : nullptr;
-            int st = (q == hipSuccess) ? WRS_OK : WRS_EDEVICE;
+            int st = (q == hipSuccess && b.ok) ? WRS_OK : WRS_EDEVICE;
             if (r->op == OP_BUILD && tb) {
                 if (st == WRS_OK) st = b.h_status ? b.h_status[r->build_index] : WRS_EDEVICE;
                 tb->state = (st == WRS_OK) ? T_READY : T_FAILED;
@@ -192,29 +202,34 @@ static void retire(Server& S, bool block) {
             finish_request(S, r, st, t);
         }
         for (auto& p : b.scratch) S.pool.release(p.first, p.second);
-        (void)hipEventDestroy(b.ev);
+        if (b.ev) (void)hipEventDestroy(b.ev);
         S.slot_busy[b.slot] = false;
         S.running.pop_front();
         S.cv_done.notify_all();
     }
 }
 
+// Drop the least recently used idle table (lock held); false if none is idle.
+static bool evict_lru(Server& S) {
+    Table* victim = nullptr;
+    for (auto& kv : S.tables) {
+        Table* t = kv.second.get();
+        if (t->refs == 0 && (t->state == T_READY || t->state == T_FAILED) &&
+            (!victim || t->last_use < victim->last_use))
+            victim = t;
+    }
+    if (!victim) return false;
+    S.pool.release(victim->d_table, victim->table_bytes);
+    S.pool.release(victim->sc, 256);
+    if (victim->ready) (void)hipEventDestroy(victim->ready);
+    S.tables.erase(victim->id);
+    return true;
+}
+
 // Drop least recently used idle tables until `need` bytes fit (lock held).
 static bool make_room(Server& S, size_t need) {
-    while (S.pool.used() + need > S.cfg.hbm_budget_bytes) {
-        Table* victim = nullptr;
-        for (auto& kv : S.tables) {
-            Table* t = kv.second.get();
-            if (t->refs == 0 && (t->state == T_READY || t->state == T_FAILED) &&
-                (!victim || t->last_use < victim->last_use))
-                victim = t;
-        }
-        if (!victim) return false;
-        S.pool.release(victim->d_table, victim->table_bytes);
-        S.pool.release(victim->sc, 256);
-        if (victim->ready) (void)hipEventDestroy(victim->ready);
-        S.tables.erase(victim->id);
-    }
+    while (S.pool.used() + need > S.cfg.hbm_budget_bytes)
+        if (!evict_lru(S)) return false;
     return true;
 }
 
@@ -225,7 +240,7 @@ static bool issue(Server& S) {
     for (int i = 0; i < (int)S.slot_busy.size(); ++i)
         if (!S.slot_busy[i]) { slot = i; break; }
     if (slot < 0 || S.queue.empty()) return false;
-    const int maxb = S.cfg.one_at_a_time ? 1 : std::max(1, S.cfg.max_batch);
+    const int maxb = S.maxb;
     std::vector<Request*> take;
     std::vector<Request*> bld, smp;
     std::vector<std::pair<void*, size_t>> scratch;
@@ -235,17 +250,36 @@ static bool issue(Server& S) {
         if (r->op == OP_BUILD) {
             const size_t wsb = build_ws_bytes(tb->n) + 256;
             const size_t need = tb->table_bytes + wsb + 256;
-            if (!make_room(S, need)) break;  // wait for memory (FIFO: no overtaking)
-            tb->d_table = (wrs_entry*)S.pool.alloc(tb->table_bytes);
-            void* ws = S.pool.alloc(wsb);
-            tb->sc = (BuildScalars*)S.pool.alloc(256);
-            if (!tb->d_table || !ws || !tb->sc) {  // fragmentation: undo and wait
-                S.pool.release(tb->d_table, tb->table_bytes);
-                S.pool.release(ws, wsb);
-                S.pool.release(tb->sc, 256);
-                tb->d_table = nullptr;
-                tb->sc = nullptr;
-                break;
+            void* ws = nullptr;
+            bool placed = make_room(S, need);
+            if (placed) {
+                tb->d_table = (wrs_entry*)S.pool.alloc(tb->table_bytes);
+                ws = S.pool.alloc(wsb);
+                tb->sc = (BuildScalars*)S.pool.alloc(256);
+                if (!tb->d_table || !ws || !tb->sc) {  // fragmentation: undo
+                    S.pool.release(tb->d_table, tb->table_bytes);
+                    S.pool.release(ws, wsb);
+                    S.pool.release(tb->sc, 256);
+                    tb->d_table = nullptr;
+                    tb->sc = nullptr;
+                    placed = false;
+                }
+            }
+            if (!placed) {
+                if (evict_lru(S)) continue;  // fragmented: free one more idle table, try again
+                if (take.empty() && S.running.empty()) {
+                    // Nothing runs and nothing idle can go: the budget is held by
+                    // tables that requests queued behind this one still need, so
+                    // waiting would never end.
+                    set_error("wrs_serve: build of %lld items does not fit beside the tables pending requests hold",
+                              (long long)tb->n);
+                    tb->state = T_FAILED;
+                    tb->status = WRS_ENOMEM;
+                    S.queue.pop_front();
+                    finish_request(S, r, WRS_ENOMEM, now_s());
+                    continue;
+                }
+                break;  // wait for running batches to retire (FIFO: no overtaking)
             }
             scratch.push_back({ws, wsb});
             tb->state = T_BUILDING;
@@ -266,18 +300,10 @@ static bool issue(Server& S) {
     hipStream_t st = S.streams[slot];
     // descriptors: builds first, then samples, each its own job table
     const int nb = (int)bld.size(), ns = (int)smp.size();
+    // bb + sb + status_bytes(nb) <= slot_bytes(max batch): the slot's buffers hold it
     const size_t bb = nb ? descriptor_bytes(nb) : 0, sb = ns ? descriptor_bytes(ns) : 0;
-    const size_t stb = nb ? status_bytes(nb) : 0;  // build statuses, device -> pinned host
-    const size_t need_stage = bb + sb + stb;
-    if (S.staging_bytes[slot] < need_stage) {
-        if (S.staging[slot]) (void)hipHostFree(S.staging[slot]);
-        S.staging[slot] = nullptr;
-        if (hipHostMalloc((void**)&S.staging[slot], need_stage) != hipSuccess) S.staging[slot] = nullptr;
-        S.staging_bytes[slot] = S.staging[slot] ? need_stage : 0;
-    }
-    char* dev_desc = (char*)S.pool.alloc(need_stage);
-    if (dev_desc) scratch.push_back({dev_desc, need_stage});
-    bool ok = S.staging[slot] && dev_desc;
+    char* dev_desc = S.dev_desc[slot];
+    bool ok = true;
     // samples wait for tables built by batches still running on other streams
     for (Request* r : smp) {
         Table* tb = S.tables[r->table_id].get();
@@ -360,9 +386,16 @@ static bool issue(Server& S) {
     b.reqs = take;
     b.scratch = scratch;
     b.h_status = (ok && nb) ? (const int32_t*)(S.staging[slot] + bb + sb) : nullptr;
-    (void)hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
-    (void)hipEventRecord(b.ev, st);
+    if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+        b.ev = nullptr;
+        ok = false;
+    } else if (hipEventRecord(b.ev, st) != hipSuccess) {
+        ok = false;
+    }
+    b.ok = ok;
     if (!ok) {
+        // retire() fails every request of the batch; wait so that its slot
+        // buffers are free again when the slot is
         set_error("wrs_serve: batch launch failed");
         (void)hipStreamSynchronize(st);
     }
@@ -396,31 +429,55 @@ static void worker_main(Server* S) {
 
 using namespace wrs;
 
+// Streams and pinned buffers of a server (its pool frees itself).
+static void release_slots(Server* S) {
+    for (auto st : S->streams) (void)hipStreamDestroy(st);
+    for (auto p : S->staging)
+        if (p) (void)hipHostFree(p);
+    S->streams.clear();
+    S->staging.clear();
+}
+
 extern "C" int wrs_serve_create(const wrs_serve_config* cfg, void** srv) {
-    if (!cfg || !srv || cfg->hbm_budget_bytes < (1u << 20)) { set_error("wrs_serve_create: bad config"); return WRS_EINVAL; }
+    if (!cfg || !srv || cfg->hbm_budget_bytes < (1u << 20) || cfg->max_batch < 1 ||
+        cfg->max_batch > WRS_SERVE_MAX_BATCH || cfg->inflight < 1 || cfg->inflight > WRS_SERVE_MAX_INFLIGHT) {
+        set_error("wrs_serve_create: bad config");
+        return WRS_EINVAL;
+    }
     auto* S = new Server();
     S->cfg = *cfg;
-    if (S->cfg.max_batch < 1) S->cfg.max_batch = 1;
-    if (S->cfg.inflight < 1) S->cfg.inflight = 1;
     if (S->cfg.one_at_a_time) S->cfg.inflight = 1;
+    S->maxb = S->cfg.one_at_a_time ? 1 : S->cfg.max_batch;
     (void)hipGetDevice(&S->device);
     if (!S->pool.init(cfg->hbm_budget_bytes)) {
         delete S;
         set_error("wrs_serve_create: cannot reserve %zu bytes", cfg->hbm_budget_bytes);
         return WRS_ENOMEM;
     }
+    const size_t sbytes = slot_bytes(S->maxb);
     for (int i = 0; i < S->cfg.inflight; ++i) {
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            release_slots(S);
             delete S;
             set_error("wrs_serve_create: stream creation failed");
             return WRS_EDEVICE;
         }
         S->streams.push_back(st);
-        S->staging.push_back(nullptr);
-        S->staging_bytes.push_back(0);
+        char* h = nullptr;
+        if (hipHostMalloc((void**)&h, sbytes) != hipSuccess) h = nullptr;
+        S->staging.push_back(h);
+        char* d = (char*)S->pool.alloc(sbytes);
+        S->dev_desc.push_back(d);
         S->slot_busy.push_back(false);
+        if (!h || !d) {
+            release_slots(S);
+            delete S;
+            set_error("wrs_serve_create: cannot reserve %zu bytes of descriptors per slot", sbytes);
+            return WRS_ENOMEM;
+        }
     }
+    S->reserved = S->pool.used();
     S->worker = std::thread(worker_main, S);
     *srv = S;
     return WRS_OK;
@@ -430,7 +487,8 @@ extern "C" int wrs_serve_submit_build(void* srv, const float* d_w, int64_t n, ui
     auto* S = (Server*)srv;
     if (!S || !d_w || !table_id || !req || n < 1 || n > 2147483647LL) { set_error("wrs_serve_submit_build: bad arguments"); return WRS_EINVAL; }
     const size_t need = (size_t)n * sizeof(wrs_entry) + build_ws_bytes(n) + 1024;
-    if (need > S->cfg.hbm_budget_bytes) { set_error("wrs_serve_submit_build: request exceeds the HBM budget"); return WRS_ENOMEM; }
+    const size_t avail = S->cfg.hbm_budget_bytes > S->reserved ? S->cfg.hbm_budget_bytes - S->reserved : 0;
+    if (need > avail) { set_error("wrs_serve_submit_build: request exceeds the HBM budget"); return WRS_ENOMEM; }
     std::lock_guard<std::mutex> g(S->mu);
     auto t = std::make_unique<Table>();
     t->id = S->next_id++;
@@ -577,9 +635,7 @@ extern "C" int wrs_serve_destroy(void* srv) {
     if (S->worker.joinable()) S->worker.join();
     for (auto& kv : S->tables)
         if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
-    for (auto st : S->streams) (void)hipStreamDestroy(st);
-    for (auto p : S->staging)
-        if (p) (void)hipHostFree(p);
+    release_slots(S);
     delete S;
     return WRS_OK;
 }

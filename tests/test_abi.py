@@ -43,9 +43,13 @@ def test_host_validation_without_gpu_work(wrs):
     assert "null" in wrs.last_error()
     assert L.wrs_alias_sample(None, 10, 0, 0, 0, 10, None, None) == wrs.EINVAL
     assert L.wrs_sample_wor(None, 10, 1, 0, 0, None, None, 0, None) == wrs.EINVAL
-    cfg = wrs.ServeConfig(1024, 8, 0, 1)  # budget below 1 MiB is rejected before touching the device
+    # server configurations out of range are rejected before touching the device:
+    # a budget below 1 MiB, batches or concurrent batches outside their limits
     srv = ctypes.c_void_p()
-    assert L.wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.EINVAL
+    for cfg in (wrs.ServeConfig(1024, 8, 0, 1), wrs.ServeConfig(1 << 30, 0, 0, 1),
+                wrs.ServeConfig(1 << 30, wrs.SERVE_MAX_BATCH + 1, 0, 1), wrs.ServeConfig(1 << 30, 8, 0, 0),
+                wrs.ServeConfig(1 << 30, 8, 0, wrs.SERVE_MAX_INFLIGHT + 1)):
+        assert L.wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.EINVAL
 
 
 def test_workspace_depends_on_n_only(wrs):

@@ -251,3 +251,71 @@ def test_serve_evicts_idle_tables_within_budget(wrs):
         assert L.wrs_serve_submit_sample(srv, tids[0], 10, 1, out.data_ptr(), ctypes.byref(rid)) == wrs.ENOTFOUND
     finally:
         L.wrs_serve_destroy(srv)
+
+
+def test_serve_unadmittable_build_fails_instead_of_waiting(wrs):
+    """With one batch in flight, a long draw holds the slot while a build and
+    draws from every resident table queue behind it.  When the slot frees up,
+    the build can neither fit beside the tables those draws need nor evict one:
+    it fails with ENOMEM (and so does a later draw from its table) instead of
+    waiting for ever, and the draws behind it still equal single calls."""
+    import ctypes
+    import time
+    import torch
+    L = wrs.lib()
+    n = 1 << 20
+    T = n * 8
+    Wk = L.wrs_workspace_bytes(wrs.OP_BUILD, n, 0)
+    budget = 3 * T + Wk + T // 2  # three resident tables and one build, not a fourth table besides
+    cfg = wrs.ServeConfig(budget, 8, 0, 1)
+    srv = ctypes.c_void_p()
+    assert L.wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.OK
+    try:
+        tid, rid, st, done = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int(), ctypes.c_int()
+        w = [torch.from_numpy(workloads.uniform(n, 70 + i)).to("cuda:0") for i in range(4)]
+        tids = []
+        for i in range(3):
+            say("serve: resident table", i)
+            assert L.wrs_serve_submit_build(srv, w[i].data_ptr(), n, ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
+            tids.append(tid.value)
+            assert L.wrs_serve_wait(srv, rid.value, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
+        s = wrs.ServeStats()
+        assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
+        launches = s.launches
+        kx = 1 << 30
+        out_x = torch.empty(kx, dtype=torch.int32, device="cuda:0")
+        say("serve: a long draw in the only slot")
+        assert L.wrs_serve_submit_sample(srv, tids[2], kx, 9, out_x.data_ptr(), ctypes.byref(rid)) == wrs.OK
+        r_x = rid.value
+        t0 = time.time()
+        while s.launches == launches:
+            assert time.time() - t0 < 10, "the long draw was never issued"
+            assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
+        # queued behind it: a build that needs a fourth table, then draws from all three
+        assert L.wrs_serve_submit_build(srv, w[3].data_ptr(), n, ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
+        t_c, r_c = tid.value, rid.value
+        outs, r_s = [], []
+        for i in range(3):
+            o = torch.full((5000,), -1, dtype=torch.int32, device="cuda:0")
+            assert L.wrs_serve_submit_sample(srv, tids[i], 5000, 20 + i, o.data_ptr(), ctypes.byref(rid)) == wrs.OK
+            outs.append(o)
+            r_s.append(rid.value)
+        assert L.wrs_serve_poll(srv, r_x, ctypes.byref(done), ctypes.byref(st)) == wrs.OK
+        if done.value:
+            pytest.skip("the long draw ended before the queue was formed behind it")
+        assert L.wrs_serve_wait(srv, r_c, ctypes.byref(st)) == wrs.OK and st.value == wrs.ENOMEM
+        for i, r in enumerate(r_s):
+            assert L.wrs_serve_wait(srv, r, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
+            _, smp = single(wrs, w[i], n, 5000, 20 + i, 0)
+            assert np.array_equal(outs[i].cpu().numpy(), smp), i
+        assert L.wrs_serve_wait(srv, r_x, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
+        _, smp = single(wrs, w[2], n, 1 << 16, 9, 0)
+        assert np.array_equal(out_x[: 1 << 16].cpu().numpy(), smp)
+        # a draw from the failed table fails at once (nothing is launched for it)
+        o = torch.full((10,), -1, dtype=torch.int32, device="cuda:0")
+        assert L.wrs_serve_submit_sample(srv, t_c, 10, 1, o.data_ptr(), ctypes.byref(rid)) == wrs.OK
+        assert L.wrs_serve_wait(srv, rid.value, ctypes.byref(st)) == wrs.OK and st.value == wrs.ENOMEM
+        assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
+        assert s.failed == 2 and s.bytes_peak <= budget
+    finally:
+        L.wrs_serve_destroy(srv)
