@@ -63,6 +63,12 @@ def _load():
         "orc_twolevel_build": (ctypes.c_int, [P, i64, i64, P, P, P, P]),
         "orc_twolevel_sample": (ctypes.c_int, [P, P, P, P, i64, i64, u64, u32, u64, i64, P]),
         "orc_twolevel_sample_at": (ctypes.c_int, [P, P, P, P, i64, i64, u64, u32, P, i64, P]),
+        "orc_os_log": (ctypes.c_double, [ctypes.c_double]),
+        "orc_os_sqrt": (ctypes.c_double, [ctypes.c_double]),
+        "orc_os_lfact": (ctypes.c_double, [ctypes.c_double]),
+        "orc_os_binomial": (ctypes.c_int, [i64, ctypes.c_double, u64, u64, u32, P]),
+        "orc_os_groups": (ctypes.c_int, [P, i64, P, P, P, P, P, P]),
+        "orc_os_sample": (ctypes.c_int, [P, i64, i64, u64, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -254,3 +260,53 @@ def twolevel_sample_at(t_top, a_top, t, alias, block, seed, stream_id, counters)
                                                                     int(block), seed, stream_id, _ptr(c), c.size,
                                                                     _ptr(out)))
     return out
+
+
+# --- output-sensitive sampling with replacement (Section 5) -------------------
+
+def os_log(x):
+    """ln x from IEEE basic operations (the binomial generator's logarithm)."""
+    return _load().orc_os_log(float(x))
+
+
+def os_sqrt(x):
+    return _load().orc_os_sqrt(float(x))
+
+
+def os_lfact(j):
+    """ln(j!) (sum of logarithms below 10, Stirling's series above)."""
+    return _load().orc_os_lfact(float(j))
+
+
+def os_binomial(m, rho, seed, heap, tag):
+    """Binomial(m, rho) drawn with the counter blocks (heap, tag, attempt)."""
+    out = ctypes.c_int64()
+    _check("orc_os_binomial", _load().orc_os_binomial(int(m), float(rho), seed, heap, tag, ctypes.byref(out)))
+    return out.value
+
+
+def os_groups(w):
+    """Groups of the output-sensitive structure -> (order, exps, starts, counts):
+    order[j] = item at position j (groups heaviest first, items by index)."""
+    w = _f32(w)
+    order = np.empty(w.size, np.int32)
+    ge = np.empty(300, np.int32)
+    gs = np.empty(300, np.int64)
+    gc = np.empty(300, np.int64)
+    u, npos = ctypes.c_int64(), ctypes.c_int64()
+    _check("orc_os_groups", _load().orc_os_groups(_ptr(w), w.size, _ptr(order), _ptr(ge), _ptr(gs), _ptr(gc),
+                                                  ctypes.byref(u), ctypes.byref(npos)))
+    return order[: npos.value], ge[: u.value], gs[: u.value], gc[: u.value]
+
+
+def os_sample(w, k, seed):
+    """k draws with replacement, output-sensitively (Section 5) -> (items,
+    counts): the distinct items drawn, ascending, and their multiplicities."""
+    w = _f32(w)
+    cap = max(1, min(int(k), w.size))
+    items = np.empty(cap, np.int32)
+    counts = np.empty(cap, np.int64)
+    s = ctypes.c_int64()
+    _check("orc_os_sample", _load().orc_os_sample(_ptr(w), w.size, int(k), seed, _ptr(items), _ptr(counts),
+                                                  ctypes.byref(s)))
+    return items[: s.value], counts[: s.value]

@@ -32,6 +32,8 @@
  *   orc_sample_wor      the k smallest keys form the sample without replacement
  *                       (problem WRS-N of Section 1).
  *   orc_permutation     problem WRP (Sections 1 and 7): all items in key order.
+ *   orc_os_*            output-sensitive sampling with replacement (Section 5),
+ *                       in wrs_oracle_os.cpp.
  *
  * Readings where the paper leaves details open are listed in the project's
  * design notes; the ones that affect results are repeated at the functions.
