@@ -53,7 +53,8 @@ enum {
     WRS_ENOTFOUND = -6  /* server: unknown table or request id */
 };
 
-enum { WRS_OP_BUILD = 1, WRS_OP_WOR = 2, WRS_OP_BUILD_PLUS = 3, WRS_OP_PERM = 4, WRS_OP_TWOLEVEL = 5 };
+enum { WRS_OP_BUILD = 1, WRS_OP_WOR = 2, WRS_OP_BUILD_PLUS = 3, WRS_OP_PERM = 4, WRS_OP_TWOLEVEL = 5,
+       WRS_OP_OS = 6 };
 
 /* Items per block (meta-item) of the 2-level tables (part of their layout). */
 #define WRS_TWOLEVEL_BLOCK 2048
@@ -64,8 +65,9 @@ enum { WRS_OP_BUILD = 1, WRS_OP_WOR = 2, WRS_OP_BUILD_PLUS = 3, WRS_OP_PERM = 4,
 /* Bytes of device workspace needed by wrs_alias_build (op = WRS_OP_BUILD, k
  * ignored), wrs_alias_build_plus (op = WRS_OP_BUILD_PLUS, k ignored),
  * wrs_sample_wor (op = WRS_OP_WOR), wrs_permutation (op = WRS_OP_PERM, k
- * ignored) or wrs_twolevel_build (op = WRS_OP_TWOLEVEL, k ignored).  Depends
- * on n (and k) only.
+ * ignored), wrs_twolevel_build (op = WRS_OP_TWOLEVEL, k ignored) or
+ * wrs_os_build and wrs_os_sample (op = WRS_OP_OS; k = the largest sample the
+ * workspace serves, 0 for a build only).  Depends on n (and k) only.
  * Returns 0 for invalid arguments. */
 size_t wrs_workspace_bytes(int op, int64_t n, int64_t k);
 
@@ -113,6 +115,44 @@ int wrs_alias_build_plus(const float* d_w, int64_t n, wrs_entry* d_table,
  * d_out is then unspecified. */
 int wrs_permutation(const float* d_w, int64_t n, uint64_t seed, uint32_t stream_id, int32_t* d_out,
                     void* d_ws, size_t ws_bytes, void* stream);
+
+/* Output-sensitive sampling with replacement (Section 5): a sample of k draws
+ * returned as the s distinct items drawn with their multiplicities, in
+ * expected work O(s + log n) after a build.
+ * Structure: the items with w > 0 are grouped by binary exponent (weights
+ * within a factor of two; groups heaviest first, items of a group by index);
+ * a divide-and-conquer tree over the groups and one over each group's items
+ * split a node asked for m draws by a binomial variate (always in the top
+ * tree, at m >= 2 inside a group), and a group node asked for one draw takes
+ * it from the group's bucket table by rejection.  A node over [lo, hi) splits
+ * at floor((lo + hi)/2).  The draws of node h are the Philox-4x32-10 counter
+ * blocks (h mod 2^32, h >> 32, tag, attempt) under key `seed`, tag = the group's
+ * position or 0xFFFFFFFF in the top tree; binomial variates by inversion below
+ * mean 10, else by transformed rejection (BTRS), both in IEEE basic operations,
+ * so results are a pure function of (weights, k, seed).
+ * Bytes of the structure for n items (about 16 per item); 0 if n is out of
+ * range. */
+size_t wrs_os_bytes(int64_t n);
+
+/* Build the structure for d_w[0..n) (FP32 weights, device) into d_os
+ * (wrs_os_bytes(n) bytes, device, 256-byte aligned; it holds no pointer, so it
+ * may be copied or moved).  d_ws: wrs_workspace_bytes(WRS_OP_OS, n, 0) bytes
+ * or more (device, 256-byte aligned), free again when the build has run.  A
+ * negative, NaN or infinite weight, or no positive weight, sets the
+ * structure's status (wrs_status(d_os)) to WRS_EDOMAIN. */
+int wrs_os_build(const float* d_w, int64_t n, void* d_os, size_t os_bytes, void* d_ws, size_t ws_bytes,
+                 void* stream);
+
+/* Draw k (0 <= k <= 2^31 - 1) items with replacement from a built structure
+ * of n items, seed `seed`.  Writes the s distinct items drawn to d_items and
+ * their multiplicities (>= 1, summing to k) to d_counts, in no particular
+ * order, and s to *d_s (device int64).  d_items, d_counts: min(k, n) int32
+ * each (device, 4-byte aligned).  d_ws: wrs_workspace_bytes(WRS_OP_OS, n, k)
+ * bytes (device, 256-byte aligned); its status word (wrs_status(d_ws)) is
+ * the structure's build status, or WRS_EDEVICE if a bound that the method
+ * never reaches was reached; *d_s is 0 unless the status is WRS_OK. */
+int wrs_os_sample(const void* d_os, int64_t n, int64_t k, uint64_t seed, int32_t* d_items, int32_t* d_counts,
+                  int64_t* d_s, void* d_ws, size_t ws_bytes, void* stream);
 
 /* Build a 2-level alias table (Section 4.4, replicated top level).  The items
  * are cut into blocks of WRS_TWOLEVEL_BLOCK consecutive items; block g is a

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwrs.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EDEVICE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-OP_BUILD, OP_WOR, OP_BUILD_PLUS, OP_PERM, OP_TWOLEVEL = 1, 2, 3, 4, 5
+OP_BUILD, OP_WOR, OP_BUILD_PLUS, OP_PERM, OP_TWOLEVEL, OP_OS = 1, 2, 3, 4, 5, 6
 TWOLEVEL_BLOCK = 2048  # items per block (meta-item) of the 2-level tables
 PSAPLUS_BLOCK = 2048  # items per greedy block of alias_build_plus
 SERVE_MAX_BATCH = 4096  # limits of ServeConfig.max_batch and ServeConfig.inflight
@@ -60,6 +60,12 @@ EXPORTS = {
                                             ctypes.c_size_t, ctypes.c_void_p]),
     "wrs_permutation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "wrs_os_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+    "wrs_os_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "wrs_os_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.c_void_p]),
     "wrs_twolevel_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "wrs_twolevel_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
@@ -185,6 +191,25 @@ def alias_build_plus(w, n, table, ws, stream=None):
 def permutation(w, n, seed, stream_id, out, ws, stream=None):
     """Weighted random permutation of the n items into out (int32)."""
     _check("wrs_permutation", lib().wrs_permutation(_ptr(w), n, seed, stream_id, _ptr(out), _ptr(ws), ws.numel() if hasattr(ws, "numel") else ws_bytes_of(ws), _stream(stream)))
+
+
+def new_os(n: int, device="cuda"):
+    """Device memory for an output-sensitive sampling structure of n items."""
+    import torch
+    return torch.empty(max(lib().wrs_os_bytes(n), 256), dtype=torch.uint8, device=device)
+
+
+def os_build(w, n, os_, ws, stream=None):
+    """Output-sensitive sampling structure (Section 5) for the n weights."""
+    _check("wrs_os_build", lib().wrs_os_build(_ptr(w), n, _ptr(os_), os_.numel(), _ptr(ws), ws.numel(),
+                                              _stream(stream)))
+
+
+def os_sample(os_, n, k, seed, items, counts, s, ws, stream=None):
+    """k draws with replacement: distinct items into items, multiplicities into
+    counts (min(k, n) int32 each, unordered), their number into s (int64[1])."""
+    _check("wrs_os_sample", lib().wrs_os_sample(_ptr(os_), n, k, seed, _ptr(items), _ptr(counts), _ptr(s),
+                                                _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def twolevel_build(w, n, table, top, ws, stream=None):

@@ -42,6 +42,7 @@ extern "C" size_t wrs_workspace_bytes(int op, int64_t n, int64_t k) {
     if (op == WRS_OP_PERM) return perm_ws_bytes(n);
     if (op == WRS_OP_TWOLEVEL) return twolevel_ws_bytes(n);
     if (op == WRS_OP_WOR) return wor_ws_bytes(n, k);
+    if (op == WRS_OP_OS) return k <= N_MAX ? os_ws_bytes(n, k) : 0;
     return 0;
 }
 
@@ -123,6 +124,35 @@ extern "C" int wrs_permutation(const float* d_w, int64_t n, uint64_t seed, uint3
     if (((uintptr_t)d_out) & 3) { set_error("wrs_permutation: output not 4-byte aligned"); return WRS_EINVAL; }
     const int e = launch_perm(d_w, n, seed, stream_id, d_out, d_ws, (hipStream_t)stream);
     if (e != 0) return dev_fail("wrs_permutation launch", (hipError_t)e);
+    return WRS_OK;
+}
+
+extern "C" size_t wrs_os_bytes(int64_t n) { return (n < 1 || n > N_MAX) ? 0 : os_bytes(n); }
+
+extern "C" int wrs_os_build(const float* d_w, int64_t n, void* d_os, size_t os_bytes_, void* d_ws, size_t ws_bytes,
+                            void* stream) {
+    g_err[0] = 0;
+    if (!d_w || !d_os || !d_ws) { set_error("wrs_os_build: null pointer"); return WRS_EINVAL; }
+    if (n < 1 || n > N_MAX) { set_error("wrs_os_build: n = %lld out of [1, 2^31-1]", (long long)n); return WRS_EINVAL; }
+    if (os_bytes_ < os_bytes(n)) { set_error("wrs_os_build: structure %zu < %zu bytes", os_bytes_, os_bytes(n)); return WRS_EINVAL; }
+    if (ws_bytes < os_ws_bytes(n, 0)) { set_error("wrs_os_build: workspace %zu < %zu bytes", ws_bytes, os_ws_bytes(n, 0)); return WRS_EINVAL; }
+    if ((((uintptr_t)d_os) | ((uintptr_t)d_ws)) & 255) { set_error("wrs_os_build: structure or workspace not 256-byte aligned"); return WRS_EINVAL; }
+    const int e = launch_os_build(d_w, n, d_os, d_ws, (hipStream_t)stream);
+    if (e != 0) return dev_fail("wrs_os_build launch", (hipError_t)e);
+    return WRS_OK;
+}
+
+extern "C" int wrs_os_sample(const void* d_os, int64_t n, int64_t k, uint64_t seed, int32_t* d_items,
+                             int32_t* d_counts, int64_t* d_s, void* d_ws, size_t ws_bytes, void* stream) {
+    g_err[0] = 0;
+    if (!d_os || !d_s || !d_ws || (k > 0 && (!d_items || !d_counts))) { set_error("wrs_os_sample: null pointer"); return WRS_EINVAL; }
+    if (n < 1 || n > N_MAX) { set_error("wrs_os_sample: n = %lld out of [1, 2^31-1]", (long long)n); return WRS_EINVAL; }
+    if (k < 0 || k > N_MAX) { set_error("wrs_os_sample: k = %lld out of [0, 2^31-1]", (long long)k); return WRS_EINVAL; }
+    if (ws_bytes < os_ws_bytes(n, k)) { set_error("wrs_os_sample: workspace %zu < %zu bytes", ws_bytes, os_ws_bytes(n, k)); return WRS_EINVAL; }
+    if ((((uintptr_t)d_os) | ((uintptr_t)d_ws)) & 255) { set_error("wrs_os_sample: structure or workspace not 256-byte aligned"); return WRS_EINVAL; }
+    if ((((uintptr_t)d_items) | ((uintptr_t)d_counts)) & 3 || ((uintptr_t)d_s) & 7) { set_error("wrs_os_sample: outputs misaligned"); return WRS_EINVAL; }
+    const int e = launch_os_sample(d_os, n, k, seed, d_items, d_counts, d_s, d_ws, (hipStream_t)stream);
+    if (e != 0) return dev_fail("wrs_os_sample launch", (hipError_t)e);
     return WRS_OK;
 }
 

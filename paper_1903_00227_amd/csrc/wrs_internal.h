@@ -183,7 +183,20 @@ int wor_status_offset();
 
 // Weighted permutation (returns 0 or a hipError_t)
 size_t perm_ws_bytes(int64_t n);
+// Stable LSD radix passes (8-bit digits at bits first_shift + 8 p, p < passes)
+// over the keys and 32-bit values that radix_inputs() locates in a workspace
+// of perm_ws_bytes(n) bytes; *keys and *vals receive the sorted arrays.
+void radix_inputs(void* ws, int64_t n, uint64_t** keys, uint32_t** vals);
+int launch_radix(void* ws, int64_t n, int first_shift, int passes, hipStream_t st, const uint64_t** keys,
+                 const uint32_t** vals);
 int launch_perm(const float* w, int64_t n, uint64_t seed, uint32_t sid, int32_t* out, void* ws, hipStream_t st);
+
+// Output-sensitive sampling with replacement (wrs_os.hip).
+size_t os_bytes(int64_t n);
+size_t os_ws_bytes(int64_t n, int64_t k);
+int launch_os_build(const float* d_w, int64_t n, void* d_os, void* d_ws, hipStream_t st);
+int launch_os_sample(const void* d_os, int64_t n, int64_t k, uint64_t seed, int32_t* d_items, int32_t* d_counts,
+                     int64_t* d_s, void* d_ws, hipStream_t st);
 
 // Error reporting for the C ABI.
 void set_error(const char* fmt, ...);

@@ -416,4 +416,38 @@ int launch_perm(const float* d_w, int64_t n, uint64_t seed, uint32_t sid, int32_
     return 0;
 }
 
+void radix_inputs(void* ws, int64_t n, uint64_t** keys, uint32_t** vals) {
+    const PermLayout P = perm_layout(ws, n);
+    *keys = P.kA;
+    *vals = P.vA;
+}
+
+int launch_radix(void* ws, int64_t n, int first_shift, int passes, hipStream_t st, const uint64_t** keys,
+                 const uint32_t** vals) {
+    const PermLayout P = perm_layout(ws, n);
+    const int64_t NB = cdiv(n, RS_TILE);
+    const int64_t NC = cdiv(NB, CH);
+    uint64_t* kin = P.kA;
+    uint32_t* vin = P.vA;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int sh = first_shift + 8 * pass;
+        uint64_t* kout = (kin == P.kA) ? P.kB : P.kA;
+        uint32_t* vout = (vin == P.vA) ? P.vB : P.vA;
+        hipLaunchKernelGGL(k_rs_up, dim3((unsigned)NB), dim3(UP_TPB), 0, st, (const uint64_t*)kin, n, sh, P.cnt, NB);
+        hipLaunchKernelGGL(k_col_part, dim3((unsigned)NC), dim3(256), 0, st, (const uint32_t*)P.cnt, NB, P.part);
+        hipLaunchKernelGGL(k_col_scan, dim3(256), dim3(256), 0, st, P.part, NC, P.tot);
+        hipLaunchKernelGGL(k_col_apply, dim3((unsigned)NC), dim3(256), 0, st, (const uint32_t*)P.cnt,
+                           (const uint32_t*)P.part, (const uint32_t*)P.tot, NB, P.off);
+        hipLaunchKernelGGL(k_rs_down, dim3((unsigned)NB), dim3(RS_TPB), 0, st, (const uint64_t*)kin,
+                           (const uint32_t*)vin, kout, vout, (const uint32_t*)P.off, n, sh, NB);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+        kin = kout;
+        vin = vout;
+    }
+    *keys = kin;
+    *vals = vin;
+    return 0;
+}
+
 }  // namespace wrs
