@@ -11,8 +11,12 @@ step's builds; `sample_gsamples_s` = sampling throughput over the step's draws;
 share of the step (the sampler); `build_hbm_frac_16B_floor` relates the build to
 its minimum HBM traffic.  Before timing, the library's autotuner picks the
 launch parameters of every size class the run uses (`tuning` lists them; they
-never change a result).  Extra objects report the batched (4096 tables) and
-served (Poisson trace) forms and the CPU oracle timed on the host.
+never change a result).  Extra objects report:
+- the greedy-block (PSA+) and 2-level builds on the same inputs;
+- output-sensitive sampling on the same inputs;
+- sampling without replacement and the weighted permutation (n = 2^26);
+- the batched (4096 tables) and served (Poisson trace) forms;
+- the CPU oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -150,6 +154,7 @@ def main():
         for fam in inputs:
             wrs.twolevel_build(inputs[fam], n, table, top, tws)
         del top, tws
+        bench_os(wrs, torch, inputs, n, k, reps=1)
         bench_perm(wrs, torch, np, workloads, reps=1)
         bench_wor(wrs, torch, np, workloads, reps=1)
         torch.cuda.synchronize()
@@ -200,6 +205,7 @@ def main():
     if not args.skip_extras:
         result["build_plus"] = bench_plus(wrs, torch, inputs, n, table)
         result["two_level"] = bench_twolevel(wrs, torch, inputs, n, table, k, out)
+        result["output_sensitive"] = bench_os(wrs, torch, inputs, n, k)
         result["without_replacement"] = bench_wor(wrs, torch, np, workloads)
         result["permutation"] = bench_perm(wrs, torch, np, workloads)
         result["batched"] = bench_batched(wrs, torch, np, workloads, not args.no_tune)
@@ -266,6 +272,41 @@ def bench_twolevel(wrs, torch, inputs, n, table, k, out, reps=5):
         res[fam] = {"build_ms": round(bms, 4), "build_gitems_s": round(n / (bms * 1e-3) / 1e9, 2),
                     "sample_ms": round(sms, 3), "sample_gsamples_s": round(k / (sms * 1e-3) / 1e9, 2)}
     del top, ws
+    return res
+
+
+def bench_os(wrs, torch, inputs, n, k, reps=3):
+    """Output-sensitive sampling with replacement (Section 5) on the same
+    resident inputs and k: build of the grouped structure, then the k draws
+    returned as distinct items with multiplicities."""
+    dev = torch.device("cuda:0")
+    log("output-sensitive sampling")
+    st = wrs.new_os(n, dev)
+    ws = wrs.new_workspace(wrs.OP_OS, n, k, dev)
+    cap = min(k, n)
+    items = torch.empty(cap, dtype=torch.int32, device=dev)
+    counts = torch.empty(cap, dtype=torch.int32, device=dev)
+    s = torch.zeros(1, dtype=torch.int64, device=dev)
+    res = {"workload": "the same n=2^28 inputs and k=2^30 draws, output-sensitive (distinct items + multiplicities)"}
+    for fam, w in inputs.items():
+        wrs.os_build(w, n, st, ws)
+        wrs.os_sample(st, n, k, 2, items, counts, s, ws)
+        torch.cuda.synchronize()
+        assert wrs.status(st) == wrs.OK and wrs.status(ws) == wrs.OK
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            wrs.os_build(w, n, st, ws)
+        e[1].record()
+        for _ in range(reps):
+            wrs.os_sample(st, n, k, 2, items, counts, s, ws)
+        e[2].record()
+        torch.cuda.synchronize()
+        bms = e[0].elapsed_time(e[1]) / reps
+        sms = e[1].elapsed_time(e[2]) / reps
+        res[fam] = {"build_ms": round(bms, 3), "sample_ms": round(sms, 3),
+                    "sample_gsamples_s": round(k / (sms * 1e-3) / 1e9, 2), "distinct": int(s.item())}
+    del st, ws, items, counts, s
     return res
 
 
