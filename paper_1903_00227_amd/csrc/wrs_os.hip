@@ -581,50 +581,67 @@ __device__ OsStep os_step(const OsLayout& L, const OsQuery& Q, OsNode nd) {
     return r;
 }
 
-// Waves take 64 consecutive nodes of a level; each wave reserves its outputs
-// and its children with one atomic each, so a wave's children stay together.
-__global__ __launch_bounds__(OS_TPB) void k_os_level(OsLayout L, OsQuery Q, int level) {
+// Blocks of OS_LVL_TPB threads take that many consecutive nodes of a level per
+// round; a round reserves the block's outputs and children with one atomic
+// each (wave counts by ballot, wave offsets in LDS), so the level's counters
+// see one atomic per OS_LVL_TPB nodes and a block's children stay together.
+constexpr int OS_LVL_TPB = 512;
+constexpr int OS_LVL_WAVES = OS_LVL_TPB / 64;
+
+__global__ __launch_bounds__(OS_LVL_TPB) void k_os_level(OsLayout L, OsQuery Q, int level) {
+    __shared__ uint32_t s_e[OS_LVL_WAVES], s_c[OS_LVL_WAVES];
+    __shared__ unsigned long long s_ebase;
+    __shared__ uint32_t s_cbase;
     const uint32_t nin = Q.sh->cnt[level];
     const OsNode* in = Q.front[level & 1];
     OsNode* out = Q.front[(level + 1) & 1];
-    const int lane = threadIdx.x & 63;
-    const uint32_t stride = gridDim.x * OS_TPB;
-    for (uint32_t base = blockIdx.x * OS_TPB + (threadIdx.x & ~63u); base < nin; base += stride) {
-        const uint32_t i = base + lane;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t stride = gridDim.x * OS_LVL_TPB;
+    for (uint32_t base = blockIdx.x * OS_LVL_TPB; base < nin; base += stride) {
+        const uint32_t i = base + threadIdx.x;
         OsStep r;
         r.emit = false;
         r.npush = 0;
         if (i < nin) r = os_step(L, Q, in[i]);
-        // outputs
         const uint64_t em = __ballot(r.emit);
-        if (em) {
-            unsigned long long eb = 0;
-            if (lane == 0) eb = atomicAdd((unsigned long long*)&Q.sh->nres, (unsigned long long)__popcll(em));
-            eb = __shfl(eb, 0);
-            if (r.emit) {
-                const uint64_t pos = eb + lanes_below(em);
-                if (pos < (uint64_t)Q.cap) {
-                    Q.items[pos] = (int32_t)r.item;
-                    Q.counts[pos] = (int32_t)r.m;
-                } else {
-                    Q.sh->status = WRS_EDEVICE;  // cannot happen: outputs are distinct positive items
-                }
+        const uint64_t m1 = __ballot(r.npush >= 1), m2 = __ballot(r.npush == 2);
+        if (lane == 0) {
+            s_e[wv] = (uint32_t)__popcll(em);
+            s_c[wv] = (uint32_t)(__popcll(m1) + __popcll(m2));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t te = 0, tc = 0;
+            for (int w = 0; w < OS_LVL_WAVES; ++w) {  // exclusive wave offsets
+                const uint32_t e = s_e[w], c = s_c[w];
+                s_e[w] = te;
+                s_c[w] = tc;
+                te += e;
+                tc += c;
+            }
+            s_ebase = te ? atomicAdd((unsigned long long*)&Q.sh->nres, (unsigned long long)te) : 0ull;
+            s_cbase = tc ? atomicAdd(&Q.sh->cnt[level + 1], tc) : 0u;
+        }
+        __syncthreads();
+        if (r.emit) {
+            const uint64_t pos = s_ebase + s_e[wv] + lanes_below(em);
+            if (pos < (uint64_t)Q.cap) {
+                Q.items[pos] = (int32_t)r.item;
+                Q.counts[pos] = (int32_t)r.m;
+            } else {
+                Q.sh->status = WRS_EDEVICE;  // cannot happen: outputs are distinct positive items
             }
         }
-        // children
-        const uint64_t m1 = __ballot(r.npush >= 1), m2 = __ballot(r.npush == 2);
-        if (m1) {
-            uint32_t pb = 0;
-            if (lane == 0) pb = atomicAdd(&Q.sh->cnt[level + 1], (uint32_t)(__popcll(m1) + __popcll(m2)));
-            pb = __shfl(pb, 0);
-            const uint64_t pos = (uint64_t)pb + lanes_below(m1) + lanes_below(m2);
+        if (r.npush) {
+            const uint64_t pos = (uint64_t)s_cbase + s_c[wv] + lanes_below(m1) + lanes_below(m2);
             if (pos + (uint64_t)r.npush <= (uint64_t)Q.cap) {
-                if (r.npush >= 1) out[pos] = r.a;
+                out[pos] = r.a;
                 if (r.npush == 2) out[pos + 1] = r.b;
-            } else if (r.npush) {
+            } else {
                 Q.sh->status = WRS_EDEVICE;  // cannot happen: frontier nodes are disjoint
             }
         }
+        __syncthreads();  // the offsets are rewritten next round
     }
 }
 
@@ -646,9 +663,9 @@ int launch_os_sample(const void* d_os, int64_t n, int64_t k, uint64_t seed, int3
     Q.counts = d_counts;
     Q.seed = seed;
     hipLaunchKernelGGL(k_os_qinit, dim3(1), dim3(64), 0, st, L, Q, k);
-    const unsigned grid = (unsigned)std::min<int64_t>(cdiv(Q.cap, OS_TPB), 4096);
+    const unsigned grid = (unsigned)std::min<int64_t>(cdiv(Q.cap, OS_LVL_TPB), 4096);
     for (int level = 0; level < OS_LEVELS; ++level)
-        hipLaunchKernelGGL(k_os_level, dim3(grid), dim3(OS_TPB), 0, st, L, Q, level);
+        hipLaunchKernelGGL(k_os_level, dim3(grid), dim3(OS_LVL_TPB), 0, st, L, Q, level);
     hipLaunchKernelGGL(k_os_qend, dim3(1), dim3(1), 0, st, Q, d_s);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : (int)e;
