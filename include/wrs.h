@@ -130,7 +130,7 @@ int wrs_permutation(const float* d_w, int64_t n, uint64_t seed, uint32_t stream_
  * position or 0xFFFFFFFF in the top tree; binomial variates by inversion below
  * mean 10, else by transformed rejection (BTRS), both in IEEE basic operations,
  * so results are a pure function of (weights, k, seed).
- * Bytes of the structure for n items (about 16 per item); 0 if n is out of
+ * Bytes of the structure for n items (about 12 per item); 0 if n is out of
  * range. */
 size_t wrs_os_bytes(int64_t n);
 

@@ -10,7 +10,7 @@
 //     order comes from two stable radix passes over the key (127 - e) << 24 | M
 //     (zero weights get key 511 << 24 and sort last);
 //   - exact prefix sums P of M over that order (u64), from which every node
-//     mass inside a group is a difference;
+//     mass inside a group, and each weight M, is a difference;
 //   - the divide-and-conquer (DC) tree over the groups: heap-indexed FP64
 //     masses, a leaf = the group's exact total scaled by 2^(e-23), an inner
 //     node = left + right.  A node over [lo, hi) splits at floor((lo + hi)/2).
@@ -71,14 +71,13 @@ struct OsLayout {
     OsGroup* groups;
     double* V;    // top-tree masses by heap index
     uint32_t* A;  // item at each position
-    uint32_t* M;  // integer weight at each position
-    uint64_t* P;  // P[j] = M[0] + ... + M[j-1], j <= n
+    uint64_t* P;  // P[j] = M[0] + ... + M[j-1], j <= n, M[j] = the integer weight at position j
 };
 
 static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct OsOffsets {
-    size_t groups, V, A, M, P, total;
+    size_t groups, V, A, P, total;
 };
 
 static OsOffsets os_offsets(int64_t n) {
@@ -87,7 +86,6 @@ static OsOffsets os_offsets(int64_t n) {
     o.groups = p; p = a256(p + sizeof(OsGroup) * OS_MAX_GROUPS);
     o.V = p;      p = a256(p + sizeof(double) * OS_HEAP);
     o.A = p;      p = a256(p + sizeof(uint32_t) * n);
-    o.M = p;      p = a256(p + sizeof(uint32_t) * n);
     o.P = p;      p = a256(p + sizeof(uint64_t) * (n + 1));
     o.total = p;
     return o;
@@ -103,7 +101,6 @@ static OsLayout os_layout(const void* os, int64_t n) {
     L.groups = (OsGroup*)(b + o.groups);
     L.V = (double*)(b + o.V);
     L.A = (uint32_t*)(b + o.A);
-    L.M = (uint32_t*)(b + o.M);
     L.P = (uint64_t*)(b + o.P);
     return L;
 }
@@ -345,7 +342,7 @@ __global__ __launch_bounds__(1024) void k_os_bscan(uint64_t* bsum, int64_t nb) {
     if (threadIdx.x == 1023) bsum[nb] = s[1023];
 }
 
-// Positions of each tile: A, M and the exclusive prefix P.
+// Positions of each tile: A and the exclusive prefix P.
 __global__ __launch_bounds__(OS_TPB) void k_os_apply(const uint64_t* __restrict__ keys,
                                                       const uint32_t* __restrict__ vals, int64_t n,
                                                       const uint64_t* __restrict__ bsum, OsLayout L, int64_t nb) {
@@ -353,14 +350,13 @@ __global__ __launch_bounds__(OS_TPB) void k_os_apply(const uint64_t* __restrict_
     __shared__ uint64_t s_p[OS_SCAN_TILE];
     __shared__ uint64_t s_t[OS_TPB];
     const int64_t base = (int64_t)blockIdx.x * OS_SCAN_TILE;
-    for (int e = 0; e < OS_SCAN_IPT; ++e) {  // coalesced: A, M and the staged weights
+    for (int e = 0; e < OS_SCAN_IPT; ++e) {  // coalesced: A and the staged weights
         const int r = e * OS_TPB + (int)threadIdx.x;
         const int64_t j = base + r;
         uint32_t m = 0;
         if (j < n) {
             m = (uint32_t)(keys[j] & 0xFFFFFFu);
             L.A[j] = vals[j];
-            L.M[j] = m;
         }
         s_m[r] = m;
     }
@@ -545,7 +541,7 @@ __device__ OsStep os_step(const OsLayout& L, const OsQuery& Q, OsNode nd) {
                 const uint4 x = os_block(Q.seed, nd.h, nd.tag, t);
                 const uint64_t u = ((uint64_t)x.y << 32) | x.x;
                 const int64_t j = (int64_t)nd.lo + (int64_t)__umul64hi(u, (uint64_t)(nd.hi - nd.lo));
-                if ((x.z >> 8) < L.M[G.start + j]) {
+                if ((x.z >> 8) < L.P[G.start + j + 1] - L.P[G.start + j]) {
                     r.emit = true;
                     r.item = L.A[G.start + j];
                     r.m = 1;
