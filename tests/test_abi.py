@@ -115,3 +115,32 @@ def test_twolevel_host_validation(wrs):
     assert L.wrs_twolevel_sample(fake, fake, 0, 0, 0, 0, 10, fake, None) == wrs.EINVAL
     assert L.wrs_twolevel_sample(fake, fake, n, 0, 0, 0, -1, fake, None) == wrs.EINVAL
     assert wrs.TWOLEVEL_BLOCK == 2048
+
+
+def test_output_sensitive_host_validation(wrs):
+    L = wrs.lib()
+    n, k = 100000, 1 << 20
+    sb = L.wrs_os_bytes(n)
+    assert 12 * n <= sb < 12 * n + (1 << 16)  # item order + prefix sums, small header and top tree
+    assert L.wrs_os_bytes(0) == 0 and L.wrs_os_bytes(1 << 31) == 0
+    wb0 = L.wrs_workspace_bytes(wrs.OP_OS, n, 0)
+    wbk = L.wrs_workspace_bytes(wrs.OP_OS, n, k)
+    assert wbk >= wb0 > 0 and wbk >= 2 * 24 * n  # two frontiers of min(k, n) nodes
+    assert L.wrs_workspace_bytes(wrs.OP_OS, n, 1 << 31) == 0
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every check below fails on the host
+    odd = ctypes.c_void_p((1 << 20) + 4)
+    assert L.wrs_os_build(None, n, fake, sb, fake, wb0, None) == wrs.EINVAL
+    assert L.wrs_os_build(fake, 0, fake, sb, fake, wb0, None) == wrs.EINVAL
+    assert L.wrs_os_build(fake, n, fake, sb - 1, fake, wb0, None) == wrs.EINVAL
+    assert "structure" in wrs.last_error()
+    assert L.wrs_os_build(fake, n, fake, sb, fake, wb0 - 1, None) == wrs.EINVAL
+    assert "workspace" in wrs.last_error()
+    assert L.wrs_os_build(fake, n, odd, sb, fake, wb0, None) == wrs.EINVAL
+    s = ctypes.c_void_p((1 << 20) + 8)
+    assert L.wrs_os_sample(None, n, k, 1, fake, fake, s, fake, wbk, None) == wrs.EINVAL
+    assert L.wrs_os_sample(fake, n, k, 1, None, fake, s, fake, wbk, None) == wrs.EINVAL
+    assert L.wrs_os_sample(fake, n, -1, 1, fake, fake, s, fake, wbk, None) == wrs.EINVAL
+    assert L.wrs_os_sample(fake, n, 1 << 31, 1, fake, fake, s, fake, wbk, None) == wrs.EINVAL
+    assert L.wrs_os_sample(fake, n, k, 1, fake, fake, s, fake, wbk - 1, None) == wrs.EINVAL
+    assert L.wrs_os_sample(fake, n, k, 1, fake, fake, odd, fake, wbk, None) == wrs.EINVAL
+    assert L.wrs_os_sample(fake, n, k, 1, fake, fake, s, odd, wbk, None) == wrs.EINVAL
