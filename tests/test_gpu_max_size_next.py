@@ -14,7 +14,10 @@ oracle for exact values):
     oracle keys of neighbouring items ascend (up to 1e-12 relative);
   - sampling without replacement (k = 2^16): ascending distinct indices, 2^20
     random unselected items all have oracle keys at or above the largest
-    selected key, and the selection is the permutation's first k items.
+    selected key, and the selection is the permutation's first k items;
+  - output-sensitive sampling (k = 2^20): distinct items in range with
+    positive weights, multiplicities summing to k, and the draws of each
+    weight group (binary exponent) within 6 sigma of k times its share of W.
 """
 import numpy as np
 import pytest
@@ -183,4 +186,43 @@ def test_max_size_wor(wrs, orc, weights):
     wrs.permutation(w, N, 6, 0, out, pws)
     assert wrs.status(pws) == wrs.OK
     assert np.array_equal(np.sort(out[:k].cpu().numpy()), s)
+
+
+def test_max_size_output_sensitive(wrs, weights):
+    import torch
+    w_np, W = weights
+    dev = torch.device("cuda:0")
+    k = 1 << 20
+    w = torch.from_numpy(w_np).to(dev)
+    st = wrs.new_os(N, dev)
+    ws = wrs.new_workspace(wrs.OP_OS, N, k, dev)
+    say("max size: output-sensitive build and sample")
+    wrs.os_build(w, N, st, ws)
+    assert wrs.status(st) == wrs.OK
+    items = torch.empty(k, dtype=torch.int32, device=dev)
+    counts = torch.empty(k, dtype=torch.int32, device=dev)
+    s = torch.zeros(1, dtype=torch.int64, device=dev)
+    wrs.os_sample(st, N, k, 4, items, counts, s, ws)
+    assert wrs.status(ws) == wrs.OK
+    del st, ws
+    s = int(s.item())
+    it, ct = items[:s], counts[:s].to(torch.int64)
+    assert int(ct.sum()) == k and int(ct.min()) >= 1 and s > k - 4096
+    srt = torch.sort(it).values
+    assert int(srt[0]) >= 0 and int(srt[-1]) < N and bool((srt[1:] > srt[:-1]).all())
+    assert bool((w[it.long()] > 0).all())
+    del w
+    # per-group masses on the host, in chunks (few groups: device atomics on
+    # a handful of bins would serialize)
+    mass = np.zeros(400)
+    for s0 in range(0, N, CHUNK):
+        c = w_np[s0:s0 + CHUNK]
+        _, e = np.frexp(c)
+        mass += np.bincount(e + 200, weights=c.astype(np.float64), minlength=400)
+        say("max size: group masses through item", s0 + c.size)
+    it_np, ct_np = it.cpu().numpy(), ct.cpu().numpy()
+    _, e_it = np.frexp(w_np[it_np])
+    g = np.bincount(e_it + 200, weights=ct_np.astype(np.float64), minlength=400)
+    p = mass / W
+    assert np.all(np.abs(g - k * p) <= 6 * np.sqrt(k * p * (1 - p)) + 1)
 
