@@ -1116,28 +1116,28 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                 uint64_t kb = (j < nhc) ? B.key[ph + j] : ~0ull;
                 uint64_t ka = (pl + i < nlx) ? A.key[pl + i] : Dend;
                 // One body for both kinds of bucket (the lanes of a wave
-                // disagree on the kind, so branches would run both ways):
-                // a light aliases the next heavy not yet emitted (ph + j), a
-                // heavy the one after it.
+                // disagree on the kind): a light aliases the next heavy not
+                // yet emitted (ph + j), a heavy the one after it.  Every LDS
+                // read is unconditional at a clamped index and both kinds'
+                // values are computed, so an iteration has no branch and its
+                // reads are issued together.
                 for (int d = d0; d < d1; ++d) {
                     const bool take_h = (j < nhc) && (i >= nlc || kb <= ka);
                     const int ia = min(pl + i, TILE - 1), ib = min(ph + j, TILE - 1);
-                    const int64_t own = take_h ? item(bbase, B.id[ib]) : item(abase, A.id[ia]);
                     const int q = ph + j + (take_h ? 1 : 0);
-                    const int32_t al = (q < nhy) ? (int32_t)item(bbase, B.id[q])
+                    const uint32_t id_a = A.id[ia], id_b = B.id[ib], id_q = B.id[min(q, TILE - 1)];
+                    const float t_a = A.t[ia];
+                    const int64_t own = take_h ? item(bbase, id_b) : item(abase, id_a);
+                    const int32_t al = (q < nhy) ? (int32_t)item(bbase, id_q)
                                                  : (nextH != FH_NONE ? nextH : (int32_t)own);
-                    const float t = take_h ? heavy_t(kb, ka, tscale) : A.t[ia];
-                    store_entry(J.table, own, t, al);
-                    if (take_h) {
-                        ++j;
-                    } else {
-                        ++i;
-                    }
-                    // one LDS read: the key at the cursor that moved
-                    const bool more = take_h ? (j < nhc) : (pl + i < nlx);
-                    const uint64_t nk = more ? (take_h ? B.key[ph + j] : A.key[pl + i]) : (take_h ? ~0ull : Dend);
-                    kb = take_h ? nk : kb;
-                    ka = take_h ? ka : nk;
+                    const float t_h = heavy_t(kb, ka, tscale);
+                    store_entry(J.table, own, take_h ? t_h : t_a, al);
+                    j += take_h ? 1 : 0;
+                    i += take_h ? 0 : 1;
+                    // the keys at both cursors; only the one that moved is taken
+                    const uint64_t nkb = B.key[min(ph + j, TILE - 1)], nka = A.key[min(pl + i, TILE - 1)];
+                    kb = take_h ? ((j < nhc) ? nkb : ~0ull) : kb;
+                    ka = take_h ? ka : ((pl + i < nlx) ? nka : Dend);
                 }
             }
         }
