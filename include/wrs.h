@@ -149,8 +149,9 @@ int wrs_os_build(const float* d_w, int64_t n, void* d_os, size_t os_bytes, void*
  * order, and s to *d_s (device int64).  d_items, d_counts: min(k, n) int32
  * each (device, 4-byte aligned).  d_ws: wrs_workspace_bytes(WRS_OP_OS, n, k)
  * bytes (device, 256-byte aligned); its status word (wrs_status(d_ws)) is
- * the structure's build status, or WRS_EDEVICE if a bound that the method
- * never reaches was reached; *d_s is 0 unless the status is WRS_OK. */
+ * the structure's build status, WRS_EINVAL if the structure was built for
+ * another n, or WRS_EDEVICE if a bound that the method never reaches was
+ * reached; *d_s is 0 unless the status is WRS_OK. */
 int wrs_os_sample(const void* d_os, int64_t n, int64_t k, uint64_t seed, int32_t* d_items, int32_t* d_counts,
                   int64_t* d_s, void* d_ws, size_t ws_bytes, void* stream);
 

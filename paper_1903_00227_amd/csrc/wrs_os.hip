@@ -483,12 +483,14 @@ struct OsQuery {
     uint64_t seed;
 };
 
-__global__ void k_os_qinit(OsLayout L, OsQuery Q, int64_t k) {
+// Reads only the header and the group table (fixed offsets), so a structure
+// built for another n is refused before any n-dependent array is touched.
+__global__ void k_os_qinit(OsLayout L, OsQuery Q, int64_t n, int64_t k) {
     const int t = threadIdx.x;  // 64 threads
     Q.sh->cnt[t] = 0;
     if (t != 0) return;
     Q.sh->nres = 0;
-    const int32_t st = L.hdr->status;
+    const int32_t st = (L.hdr->n != n) ? WRS_EINVAL : L.hdr->status;
     Q.sh->status = st;
     if (st != WRS_OK || k == 0) return;
     OsNode r;
@@ -658,7 +660,7 @@ int launch_os_sample(const void* d_os, int64_t n, int64_t k, uint64_t seed, int3
     Q.items = d_items;
     Q.counts = d_counts;
     Q.seed = seed;
-    hipLaunchKernelGGL(k_os_qinit, dim3(1), dim3(64), 0, st, L, Q, k);
+    hipLaunchKernelGGL(k_os_qinit, dim3(1), dim3(64), 0, st, L, Q, n, k);
     const unsigned grid = (unsigned)std::min<int64_t>(cdiv(Q.cap, OS_LVL_TPB), 4096);
     for (int level = 0; level < OS_LEVELS; ++level)
         hipLaunchKernelGGL(k_os_level, dim3(grid), dim3(OS_LVL_TPB), 0, st, L, Q, level);

@@ -107,6 +107,17 @@ def test_os_zero_draws_and_errors(wrs):
     ws = wrs.new_workspace(wrs.OP_OS, 64, 1)
     wrs.os_build(w, 64, st, ws)
     assert wrs.status(st) == wrs.EDOMAIN
+    # a structure queried with another n than it was built for is refused
+    w = torch.from_numpy(workloads.uniform(5000, 5)).cuda()
+    st = wrs.new_os(5000)
+    ws = wrs.new_workspace(wrs.OP_OS, 5000, 100)
+    wrs.os_build(w, 5000, st, ws)
+    assert wrs.status(st) == wrs.OK
+    items = torch.empty(100, dtype=torch.int32, device="cuda")
+    counts = torch.empty(100, dtype=torch.int32, device="cuda")
+    s = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    wrs.os_sample(st, 4000, 100, 1, items, counts, s, ws)
+    assert wrs.status(ws) == wrs.EINVAL and int(s.item()) == 0
 
 
 def test_os_ragged_mid_size(wrs):
