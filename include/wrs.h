@@ -137,9 +137,12 @@ size_t wrs_os_bytes(int64_t n);
 /* Build the structure for d_w[0..n) (FP32 weights, device) into d_os
  * (wrs_os_bytes(n) bytes, device, 256-byte aligned; it holds no pointer, so it
  * may be copied or moved).  d_ws: wrs_workspace_bytes(WRS_OP_OS, n, 0) bytes
- * or more (device, 256-byte aligned), free again when the build has run.  A
- * negative, NaN or infinite weight, or no positive weight, sets the
- * structure's status (wrs_status(d_os)) to WRS_EDOMAIN. */
+ * or more (device, 256-byte aligned), free again when the build has run.  The
+ * call blocks the calling thread until its first pass over the weights has run
+ * on the stream: it reads back one flag to sort by one 8-bit digit of the
+ * group key, or by two when a weight is zero or below 2^-128.  So it cannot be
+ * captured in a graph.  A negative, NaN or infinite weight, or no positive
+ * weight, sets the structure's status (wrs_status(d_os)) to WRS_EDOMAIN. */
 int wrs_os_build(const float* d_w, int64_t n, void* d_os, size_t os_bytes, void* d_ws, size_t ws_bytes,
                  void* stream);
 

@@ -56,7 +56,8 @@ struct OsHeader {
     int32_t u;   // nonempty groups
     int64_t n;
     int64_t np;  // positive items
-    int32_t pad[58];
+    int32_t wide;  // some sort key needs a second digit: a zero weight, or e < -128
+    int32_t pad[57];
 };
 static_assert(sizeof(OsHeader) == 256, "header is one 256-byte line");
 
@@ -263,10 +264,12 @@ __global__ void k_os_init(OsHeader* hdr, int64_t n) {
         hdr->u = 0;
         hdr->n = n;
         hdr->np = 0;
+        hdr->wide = 0;
     }
 }
 
-// Sort key (127 - e) << 24 | M of each item, value = the item; domain check.
+// Sort key (127 - e) << 24 | M of each item, value = the item; domain check;
+// one flag per wave if a key has bit 32 set (the sort then needs two digits).
 __global__ __launch_bounds__(OS_TPB) void k_os_keys(const float* __restrict__ w, int64_t n, uint64_t* keys,
                                                      uint32_t* vals, OsHeader* hdr) {
     const int64_t i = (int64_t)blockIdx.x * OS_TPB + threadIdx.x;
@@ -292,6 +295,8 @@ __global__ __launch_bounds__(OS_TPB) void k_os_keys(const float* __restrict__ w,
     }
     keys[i] = key;
     vals[i] = (uint32_t)i;
+    const uint64_t wide = __ballot((key >> 32) != 0);
+    if (wide && (threadIdx.x & 63) == __ffsll((unsigned long long)wide) - 1) atomicOr(&hdr->wide, 1);
 }
 
 __device__ uint64_t os_block_sum(uint64_t v, uint64_t* s_w) {
@@ -461,7 +466,13 @@ int launch_os_build(const float* d_w, int64_t n, void* d_os, void* d_ws, hipStre
     if (e != hipSuccess) return (int)e;
     const uint64_t* K;
     const uint32_t* V;
-    const int rc = launch_radix(d_ws, n, 24, 2, st, &K, &V);  // key bits 24..39
+    // One 8-bit digit (bits 24..31) orders the keys unless some key reaches
+    // bit 32; the flag is read on the host to skip the second pass.
+    int32_t wide = 1;
+    e = hipMemcpyAsync(&wide, &L.hdr->wide, sizeof wide, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return (int)e;
+    const int rc = launch_radix(d_ws, n, 24, wide ? 2 : 1, st, &K, &V);
     if (rc) return rc;
     hipLaunchKernelGGL(k_os_bsum, dim3((unsigned)nb), dim3(OS_TPB), 0, st, K, n, bsum);
     hipLaunchKernelGGL(k_os_bscan, dim3(1), dim3(1024), 0, st, bsum, nb);
