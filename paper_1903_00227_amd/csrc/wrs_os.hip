@@ -7,8 +7,9 @@
 //   - items with w > 0 in groups of weights within a factor of two: the group
 //     of w is its binary exponent e, w = M 2^(e-23) with integer M in
 //     [2^23, 2^24); groups heaviest first, items of a group by index.  The
-//     order comes from two stable radix passes over the key (127 - e) << 24 | M
-//     (zero weights get key 511 << 24 and sort last);
+//     order comes from stable radix passes over the key (127 - e) << 24 | M
+//     (zero weights get key 511 << 24 and sort last): one 8-bit digit, or two
+//     when a key reaches bit 32;
 //   - exact prefix sums P of M over that order (u64), from which every node
 //     mass inside a group, and each weight M, is a difference;
 //   - the divide-and-conquer (DC) tree over the groups: heap-indexed FP64
