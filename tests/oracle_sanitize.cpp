@@ -1,5 +1,6 @@
 // Runs every oracle entry point on small and edge-case inputs; built by
 // tests/test_oracle_sanitize.py with AddressSanitizer and UBSan (host code).
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -22,6 +23,11 @@ int orc_light_t_at(const float* w, int64_t n, const int64_t* idx, int64_t m, flo
 int orc_wor_keys(const float* w, int64_t n, uint64_t seed, uint32_t sid, double* keys);
 int orc_sample_wor(const float* w, int64_t n, int64_t k, uint64_t seed, uint32_t sid, int32_t* out, double* kth);
 int orc_permutation(const float* w, int64_t n, uint64_t seed, uint32_t sid, int32_t* out);
+int orc_os_binomial(int64_t m, double rho, uint64_t seed, uint64_t heap, uint32_t tag, int64_t* out);
+int orc_os_groups(const float* w, int64_t n, int32_t* order, int32_t* gexp, int64_t* gstart, int64_t* gcount,
+                  int64_t* u, int64_t* np);
+int orc_os_sample(const float* w, int64_t n, int64_t k, uint64_t seed, int32_t* items, int64_t* counts,
+                  int64_t* s);
 }
 
 static int run(const std::vector<float>& w) {
@@ -53,12 +59,25 @@ static int run(const std::vector<float>& w) {
     orc_wor_keys(w.data(), n, 9, 0, keys.data());
     orc_sample_wor(w.data(), n, (n + 1) / 2, 9, 0, out.data(), &kth);
     orc_permutation(w.data(), n, 9, 0, out.data());
+    {  // output-sensitive sampling: groups, then samples of several sizes
+        std::vector<int32_t> order(n), gexp(300), items(n);
+        std::vector<int64_t> gstart(300), gcount(300), counts(n);
+        int64_t u = 0, np = 0, s = 0;
+        orc_os_groups(w.data(), n, order.data(), gexp.data(), gstart.data(), gcount.data(), &u, &np);
+        // items and counts hold n entries, enough for min(k, n) pairs
+        for (int64_t kk : {(int64_t)0, (int64_t)1, (int64_t)7, n, 4 * n, (int64_t)1 << 30})
+            orc_os_sample(w.data(), n, kk, 5, items.data(), counts.data(), &s);
+    }
     return bad;
 }
 
 int main() {
     uint32_t c[4] = {1, 2, 3, 4}, k[2] = {5, 6}, o[4];
     orc_philox4x32_10(c, k, o);
+    int64_t x = 0;  // both binomial regimes, reflection, the degenerate cases, a bad probability
+    for (int64_t m : {(int64_t)0, (int64_t)1, (int64_t)30, (int64_t)1000, (int64_t)1 << 30})
+        for (double rho : {0.0, 1e-9, 0.1, 0.5, 0.97, 1.0}) orc_os_binomial(m, rho, 3, 7, 2, &x);
+    orc_os_binomial(10, 1.5, 3, 7, 2, &x);
     std::vector<std::vector<float>> cases = {
         {1.0f}, {0.0f, 3.0f}, {1, 2, 3, 6}, {4, 4, 4, 4}, {0, 0, 7}, {1e-40f, 0.95f}, {1e30f, 1e-30f, 1.0f},
         {-0.0f, 1.0f, 2.0f}, {1.0f, -1.0f}, {NAN, 1.0f}, {INFINITY}, {0.0f, 0.0f}};

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 def test_oracle_under_sanitizers(tmp_path):
     exe = str(tmp_path / "oracle_sanitize")
     cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
-           os.path.join(HERE, "oracle_sanitize.cpp"), os.path.join(ROOT, "oracle", "wrs_oracle.cpp"), "-o", exe]
+           os.path.join(HERE, "oracle_sanitize.cpp"), os.path.join(ROOT, "oracle", "wrs_oracle.cpp"),
+           os.path.join(ROOT, "oracle", "wrs_oracle_os.cpp"), "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     # the environment is kept as it is (a preloaded library may precede the
     # sanitizer runtime, so its link-order check is off)
