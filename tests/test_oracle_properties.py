@@ -6,7 +6,9 @@ huge ratios.  For each: the sweep and the greedy-block constructions give
 tables whose every item mass, in exact rationals, is n w_i / W up to the FP32
 rounding of the thresholds (the alias-table definition, Section 2.2); Vose's
 table reconstructs within its FP64 drift; invalid inputs give the exact error
-codes; the permutation is a permutation whose prefixes are the WRS-N samples.
+codes; the permutation is a permutation whose prefixes are the WRS-N samples;
+output-sensitive samples are distinct positive items whose multiplicities sum
+to k, grouped by binary exponent.
 """
 from fractions import Fraction
 
@@ -117,3 +119,23 @@ def test_invalid_inputs_error_codes(orc, n, bad, seed):
         with pytest.raises(orc.OracleError) as e:
             fn()
         assert e.value.code == orc.EDOMAIN
+
+
+@FAST
+@given(weights(max_n=2000), st.integers(0, 2 ** 31 - 1), st.integers(0, 2 ** 63))
+def test_output_sensitive_invariants(orc, w, k, seed):
+    """Section 5's sample: distinct positive items, ascending, multiplicities
+    summing to k, a pure function of (weights, k, seed); groups by binary
+    exponent, heaviest first, items of a group by index (against frexp)."""
+    items, counts = orc.os_sample(w, k, seed)
+    assert int(counts.sum()) == k and np.all(counts >= 1)
+    assert np.all(np.diff(items) > 0) and np.all(w[items] > 0)
+    assert items.size <= min(k, int((w > 0).sum()))
+    i2, c2 = orc.os_sample(w, k, seed)
+    assert np.array_equal(items, i2) and np.array_equal(counts, c2)
+    order, exps, starts, cnts = orc.os_groups(w)
+    pos = np.nonzero(w > 0)[0]
+    e = np.frexp(w[pos])[1] - 1
+    assert np.array_equal(order, pos[np.lexsort((pos, -e))])
+    assert list(exps) == sorted(set(e.tolist()), reverse=True)
+    assert int(cnts.sum()) == pos.size
