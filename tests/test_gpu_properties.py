@@ -4,7 +4,8 @@ one dominant item, all-equal runs, subnormals, huge ratios and integers, built
 by wrs_alias_build, wrs_alias_build_plus and wrs_twolevel_build and sampled by
 wrs_alias_sample, each against the oracle with the bars of the dedicated
 parity tests (aliases bit for bit, thresholds within their error bounds,
-draws bit-exact on the GPU's own table)."""
+draws bit-exact on the GPU's own table); output-sensitive samples of random
+size k < 2^31 bit for bit."""
 import numpy as np
 import pytest
 from hypothesis import HealthCheck, given, settings
@@ -76,3 +77,30 @@ def test_random_twolevel_match_oracle(wrs, orc, w):
     out = torch.empty(k, dtype=torch.int32, device=dev)
     wrs.twolevel_sample(top, table, n, 8, 2, 1, k, out)
     assert np.array_equal(out.cpu().numpy(), orc.twolevel_sample(tt, tp[:, 1], t, tb[:, 1], 2048, 8, 2, 1, k))
+
+
+@SETTINGS
+@given(weights(), st.integers(0, 2 ** 31 - 1), st.integers(0, 2 ** 63))
+def test_random_output_sensitive_match_oracle(wrs, orc, w, k, seed):
+    """wrs_os_build + wrs_os_sample against the oracle: the same (item,
+    multiplicity) pairs, bit for bit (compared sorted by item)."""
+    import torch
+    n = w.size
+    say("property output-sensitive", n, k)
+    dev = torch.device("cuda:0")
+    wt = torch.from_numpy(np.ascontiguousarray(w)).to(dev)
+    st_ = wrs.new_os(n, dev)
+    ws = wrs.new_workspace(wrs.OP_OS, n, k, dev)
+    wrs.os_build(wt, n, st_, ws)
+    assert wrs.status(st_) == wrs.OK
+    cap = max(1, min(k, n))
+    items = torch.empty(cap, dtype=torch.int32, device=dev)
+    counts = torch.empty(cap, dtype=torch.int32, device=dev)
+    s = torch.zeros(1, dtype=torch.int64, device=dev)
+    wrs.os_sample(st_, n, k, seed, items, counts, s, ws)
+    assert wrs.status(ws) == wrs.OK
+    s = int(s.item())
+    it, ct = items[:s].cpu().numpy(), counts[:s].cpu().numpy().astype(np.int64)
+    o = np.argsort(it)
+    ref_it, ref_ct = orc.os_sample(w, k, seed)
+    assert np.array_equal(it[o], ref_it) and np.array_equal(ct[o], ref_ct)
