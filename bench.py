@@ -205,7 +205,9 @@ def main():
     if not args.skip_extras:
         result["build_plus"] = bench_plus(wrs, torch, inputs, n, table)
         result["two_level"] = bench_twolevel(wrs, torch, inputs, n, table, k, out)
-        result["output_sensitive"] = bench_os(wrs, torch, inputs, n, k)
+        skewed = torch.from_numpy(workloads.power_law(n, 2.0, 2)).to(dev)
+        result["output_sensitive"] = bench_os(wrs, torch, inputs, n, k, skewed=skewed)
+        del skewed
         result["without_replacement"] = bench_wor(wrs, torch, np, workloads)
         result["permutation"] = bench_perm(wrs, torch, np, workloads)
         result["batched"] = bench_batched(wrs, torch, np, workloads, not args.no_tune)
@@ -275,10 +277,11 @@ def bench_twolevel(wrs, torch, inputs, n, table, k, out, reps=5):
     return res
 
 
-def bench_os(wrs, torch, inputs, n, k, reps=3):
+def bench_os(wrs, torch, inputs, n, k, reps=3, skewed=None):
     """Output-sensitive sampling with replacement (Section 5) on the same
     resident inputs and k: build of the grouped structure, then the k draws
-    returned as distinct items with multiplicities."""
+    returned as distinct items with multiplicities.  With `skewed` (resident
+    power-law s = 2 weights), also that input against the alias sampler."""
     dev = torch.device("cuda:0")
     log("output-sensitive sampling")
     st = wrs.new_os(n, dev)
@@ -287,7 +290,8 @@ def bench_os(wrs, torch, inputs, n, k, reps=3):
     items = torch.empty(cap, dtype=torch.int32, device=dev)
     counts = torch.empty(cap, dtype=torch.int32, device=dev)
     s = torch.zeros(1, dtype=torch.int64, device=dev)
-    res = {"workload": "the same n=2^28 inputs and k=2^30 draws, output-sensitive (distinct items + multiplicities)"}
+    res = {"workload": "the same n=2^28 inputs and k=2^30 draws, output-sensitive (distinct items + multiplicities); "
+                       "power2 = power law s=2 permuted (seed 2), with the alias sampler on the same input"}
     for fam, w in inputs.items():
         wrs.os_build(w, n, st, ws)
         wrs.os_sample(st, n, k, 2, items, counts, s, ws)
@@ -306,6 +310,34 @@ def bench_os(wrs, torch, inputs, n, k, reps=3):
         sms = e[1].elapsed_time(e[2]) / reps
         res[fam] = {"build_ms": round(bms, 3), "sample_ms": round(sms, 3),
                     "sample_gsamples_s": round(k / (sms * 1e-3) / 1e9, 2), "distinct": int(s.item())}
+    if skewed is not None:
+        # a more skewed input (power law s = 2, seed 2): few distinct items,
+        # the regime the method is for; the alias sampler beside it
+        w = skewed
+        wrs.os_build(w, n, st, ws)
+        wrs.os_sample(st, n, k, 2, items, counts, s, ws)
+        table = wrs.new_table(n, dev)
+        tws = wrs.new_workspace(wrs.OP_BUILD, n, 0, dev)
+        out = torch.empty(k, dtype=torch.int32, device=dev)
+        wrs.alias_build(w, n, table, tws)
+        wrs.alias_sample(table, n, 2, 0, 0, k, out)
+        torch.cuda.synchronize()
+        assert wrs.status(st) == wrs.OK and wrs.status(ws) == wrs.OK and wrs.status(tws) == wrs.OK
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            wrs.os_sample(st, n, k, 2, items, counts, s, ws)
+        e[1].record()
+        for _ in range(reps):
+            wrs.alias_sample(table, n, 2, 0, 0, k, out)
+        e[2].record()
+        torch.cuda.synchronize()
+        oms = e[0].elapsed_time(e[1]) / reps
+        ams = e[1].elapsed_time(e[2]) / reps
+        res["power2"] = {"sample_ms": round(oms, 3), "sample_gsamples_s": round(k / (oms * 1e-3) / 1e9, 2),
+                         "distinct": int(s.item()), "alias_sample_ms": round(ams, 3),
+                         "alias_sample_gsamples_s": round(k / (ams * 1e-3) / 1e9, 2)}
+        del table, tws, out
     del st, ws, items, counts, s
     return res
 
