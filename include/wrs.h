@@ -5,10 +5,16 @@
  *
  * Problems (Section 1): items 0..n-1 with weights w_i >= 0, W = sum of w_i.
  *   - alias table construction (Section 2.2 defines the table; Section 4.2 and
- *     Algorithm 3 split the sweep of Section 4.1 into independent pieces);
- *   - sampling with replacement (problem WRS-R): k independent alias queries;
+ *     Algorithm 3 split the sweep of Section 4.1 into independent pieces;
+ *     Section 4.2.1 takes greedy blocks first; Section 4.4 builds 2-level
+ *     tables);
+ *   - sampling with replacement (problem WRS-R): k independent alias queries,
+ *     or output-sensitively (Section 5): the distinct items drawn with their
+ *     multiplicities;
  *   - sampling without replacement (problem WRS-N) with exponential clocks
- *     (Section 2.3): the k items with the smallest -ln(u_i)/w_i.
+ *     (Section 2.3): the k items with the smallest -ln(u_i)/w_i;
+ *   - weighted random permutation (problem WRP, Section 7): all items in the
+ *     order of those keys.
  *
  * Conventions for every call:
  *   - Pointers named d_* are device pointers (HIP global memory of the current
