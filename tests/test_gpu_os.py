@@ -7,7 +7,9 @@ identical: bit-exact integers, compared after sorting by item (the device
 emits pairs in no particular order).  Cases span many weight groups (uniform
 weights cover exponents down to 2^-24, power laws, subnormals, zeros), the
 degenerate inputs, ragged sizes, multiplicities large enough for the
-transformed-rejection generator, and the maximum-size run's invariants.
+transformed-rejection generator, and the maximum-size run's invariants.  At
+the paper's n = 10^9 the number of distinct items drawn is checked against
+the closed form and against the output size / sample size the paper prints.
 """
 import numpy as np
 import pytest
@@ -165,3 +167,52 @@ def test_os_full_size_invariants(wrs):
     got[it_np] = ct_np
     p = w_np[top].astype(np.float64) / W
     assert np.all(np.abs(got[top] - k * p) <= 6 * np.sqrt(k * p * (1 - p)) + 1)
+
+
+def test_os_distinct_fraction_at_paper_size(wrs):
+    """n = 10^9, as in the paper's query figure: s / k of an output-sensitive
+    sample against the printed output size / sample size (golden fixture, within
+    its rtol) and against the closed form sum_i 1 - (1 - w_i/W)^k for these very
+    weights (within 6 sigma; the indicators are negatively correlated)."""
+    import json
+    import math
+    import os
+    import torch
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "golden", "paper_distinct_fraction.json")) as f:
+        g = json.load(f)
+    n = g["n"]
+    dev = torch.device("cuda:0")
+    kmax = max(c["k"] for c in g["cases"])
+    st = wrs.new_os(n, dev)
+    ws = wrs.new_workspace(wrs.OP_OS, n, kmax, dev)
+    cap = min(kmax, n)
+    items = torch.empty(cap, dtype=torch.int32, device=dev)
+    counts = torch.empty(cap, dtype=torch.int32, device=dev)
+    s = torch.zeros(1, dtype=torch.int64, device=dev)
+    gen = torch.Generator(device=dev)
+    for c in g["cases"]:
+        say("os at n = 10^9:", c["family"], c["s"], "k", c["k"])
+        if c["family"] == "uniform":
+            gen.manual_seed(41)
+            w = 1.0 - torch.rand(n, generator=gen, device=dev, dtype=torch.float32)
+        else:
+            w = torch.arange(1, n + 1, device=dev, dtype=torch.float64).pow(-c["s"]).to(torch.float32)
+        wrs.os_build(w, n, st, ws)
+        assert wrs.status(st) == wrs.OK
+        k = c["k"]
+        wrs.os_sample(st, n, k, 3, items, counts, s, ws)
+        assert wrs.status(ws) == wrs.OK
+        sv = int(s.item())
+        assert int(counts[:sv].to(torch.int64).sum()) == k
+        W = float(w.double().sum())
+        ex, var = 0.0, 0.0
+        for a in range(0, n, 1 << 27):
+            p = w[a:a + (1 << 27)].double() / W
+            q = -torch.expm1(k * torch.log1p(-p))
+            ex += float(q.sum())
+            var += float((q * (1 - q)).sum())
+        del w
+        say("  s/k", sv / k, "closed form", ex / k, "printed", c["printed"])
+        assert abs(sv - ex) <= 6 * math.sqrt(var) + 1, (c, sv, ex)
+        assert abs(sv / k - c["printed"]) <= c["rtol"] * c["printed"], (c, sv / k)

@@ -163,3 +163,17 @@ def test_special_cases():
             oracle.os_sample(x, 10, 1)
     with pytest.raises(oracle.OracleError):
         oracle.os_sample(np.zeros(5, np.float32), 10, 1)
+
+
+def test_distinct_count_matches_closed_form():
+    """s, the number of distinct items in k draws, against
+    E[X] = sum_i 1 - (1 - w_i/W)^k (the distinct-count closed form that the
+    paper's query figure plots as output size / sample size)."""
+    for s, n, k in ((1.0, 1 << 14, 1 << 16), (0.5, 1 << 12, 1 << 14), (2.0, 1 << 14, 1 << 20)):
+        w = workloads.power_law(n, s, 22)
+        items, counts = oracle.os_sample(w, k, 78)
+        p = w.astype(np.float64) / w.astype(np.float64).sum()
+        q = -np.expm1(k * np.log1p(-p))
+        ex = float(q.sum())
+        sd = math.sqrt(float((q * (1 - q)).sum()))  # indicators are negatively correlated
+        assert abs(items.size - ex) <= 6 * sd + 1, (s, items.size, ex)
