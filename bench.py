@@ -37,9 +37,10 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-# Sources with host code only (entry points, the request server): edits there
-# leave every kernel, and so its counted HBM traffic, unchanged.
-HOST_ONLY_SOURCES = ("wrs_api.hip", "wrs_serve.hip")
+# Sources with host code only (entry points, the request server and its
+# allocator): edits there leave every kernel, and so its counted HBM traffic,
+# unchanged.
+HOST_ONLY_SOURCES = ("wrs_api.hip", "wrs_serve.hip", "wrs_pool.h")
 
 
 def kernel_source_sha():

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "wrs_internal.h"
+#include "wrs_pool.h"
 
 namespace wrs {
 
@@ -33,60 +34,27 @@ static double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-// First-fit allocator over one device allocation.
+// The HBM budget: one device allocation carved by the first-fit allocator.
 class Pool {
    public:
     bool init(size_t bytes) {
         bytes = (bytes + 255) & ~(size_t)255;
-        if (hipMalloc(&base_, bytes) != hipSuccess) return false;
-        size_ = bytes;
-        free_[0] = bytes;
+        void* base = nullptr;
+        if (hipMalloc(&base, bytes) != hipSuccess) return false;
+        ff_.reset(base, bytes);
         return true;
     }
     ~Pool() {
-        if (base_) (void)hipFree(base_);
+        if (ff_.base()) (void)hipFree(ff_.base());
     }
-    void* alloc(size_t bytes) {
-        bytes = (bytes + 255) & ~(size_t)255;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                const size_t off = it->first, sz = it->second;
-                free_.erase(it);
-                if (sz > bytes) free_[off + bytes] = sz - bytes;
-                used_ += bytes;
-                peak_ = std::max(peak_, used_);
-                return (char*)base_ + off;
-            }
-        }
-        return nullptr;
-    }
-    void release(void* p, size_t bytes) {
-        if (!p) return;
-        bytes = (bytes + 255) & ~(size_t)255;
-        size_t off = (char*)p - (char*)base_;
-        used_ -= bytes;
-        auto nx = free_.lower_bound(off);
-        if (nx != free_.end() && off + bytes == nx->first) {
-            bytes += nx->second;
-            nx = free_.erase(nx);
-        }
-        if (nx != free_.begin()) {
-            auto pv = std::prev(nx);
-            if (pv->first + pv->second == off) {
-                pv->second += bytes;
-                return;
-            }
-        }
-        free_[off] = bytes;
-    }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
-    size_t size() const { return size_; }
+    void* alloc(size_t bytes) { return ff_.alloc(bytes); }
+    void release(void* p, size_t bytes) { ff_.release(p, bytes); }
+    size_t used() const { return ff_.used(); }
+    size_t peak() const { return ff_.peak(); }
+    size_t size() const { return ff_.size(); }
 
    private:
-    void* base_ = nullptr;
-    size_t size_ = 0, used_ = 0, peak_ = 0;
-    std::map<size_t, size_t> free_;
+    FirstFit ff_;
 };
 
 enum { OP_BUILD = 1, OP_SAMPLE = 2 };
