@@ -344,7 +344,9 @@ int wrs_serve_read_table(void* srv, uint64_t table_id, wrs_entry* h_table, int64
 int wrs_serve_stats(void* srv, wrs_serve_stats_t* out);
 int wrs_serve_destroy(void* srv);
 
-/* Text of the last error on this thread ("" if none). */
+/* Text of the last error on this thread ("" if none).  The request server's
+ * worker runs on a thread of its own: its failures reach the caller as
+ * request statuses (wrs_serve_wait, wrs_serve_poll), not through this text. */
 const char* wrs_last_error(void);
 
 #ifdef __cplusplus
