@@ -459,7 +459,7 @@ def bench_batched(wrs, torch, np, workloads, run_tune=True):
             "fused_hbm_frac_28B_per_item": round(28.0 * items / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def bench_served(wrs, torch, np, workloads, count=3000):
+def bench_served(wrs, torch, np, workloads, count=3000, inflight=2):
     """Poisson request stream (seed 5) at a fixed rate; continuous batching
     against one launch per request in arrival order, same trace."""
     import ctypes
@@ -487,7 +487,7 @@ def bench_served(wrs, torch, np, workloads, count=3000):
     L = wrs.lib()
 
     def run(mode, rate_hz):
-        cfg = wrs.ServeConfig(64 << 30, 256, 1 if mode == "one" else 0, 2)
+        cfg = wrs.ServeConfig(64 << 30, 256, 1 if mode == "one" else 0, inflight)
         srv = ctypes.c_void_p()
         assert L.wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.OK
         tid, rid = ctypes.c_uint64(), ctypes.c_uint64()
