@@ -386,7 +386,7 @@ static void worker_main(Server* S) {
             } else {
                 // poll the oldest batch; short sleeps keep the completion times sharp
                 lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                std::this_thread::sleep_for(std::chrono::microseconds(5));
                 lk.lock();
             }
         }
