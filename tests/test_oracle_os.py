@@ -177,3 +177,17 @@ def test_distinct_count_matches_closed_form():
         ex = float(q.sum())
         sd = math.sqrt(float((q * (1 - q)).sum()))  # indicators are negatively correlated
         assert abs(items.size - ex) <= 6 * sd + 1, (s, items.size, ex)
+
+
+def test_single_group_is_uniform():
+    """Equal weights form one group (the top tree is a single leaf): the
+    sample is uniform over the items (chi-square over 20 seeds)."""
+    n, k = 500, 20000
+    w = np.full(n, 0.75, np.float32)
+    order, exps, starts, cnts = oracle.os_groups(w)
+    assert list(exps) == [-1] and list(cnts) == [n] and np.array_equal(order, np.arange(n))
+    tot = np.zeros(n)
+    for seed in range(20):
+        items, counts = check_sample(w, k, 300 + seed)
+        tot[items] += counts
+    assert stats.chisquare(tot).pvalue > 1e-4
