@@ -792,9 +792,13 @@ extern "C" int orc_permutation(const float* w, int64_t n, uint64_t seed, uint32_
     return ORC_OK;
 }
 
+/* The keys of orc_wor_keys at the requested items only (the GPU tests check
+   sampled items at sizes where all n keys would not fit); the whole weight
+   array is validated as orc_wor_keys validates it. */
 extern "C" int orc_wor_keys_at(const float* w, int64_t n, uint64_t seed, uint32_t stream_id,
                                const int64_t* idx, int64_t m, double* keys) {
-    if (!w || !keys || !idx || n < 1 || m < 0) return ORC_EINVAL;
+    if (!w || !keys || !idx || n < 1 || n > 2147483647LL || m < 0) return ORC_EINVAL;
+    if (!valid_weights(w, n)) return ORC_EDOMAIN;
     for (int64_t s = 0; s < m; ++s) {
         int64_t i = idx[s];
         if (i < 0 || i >= n) return ORC_EINVAL;
