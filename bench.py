@@ -158,6 +158,7 @@ def main():
         bench_os(wrs, torch, inputs, n, k, reps=1)
         bench_perm(wrs, torch, np, workloads, reps=1)
         bench_wor(wrs, torch, np, workloads, reps=1)
+        bench_roofs(torch, n, k, wrs.tune_get(wrs.TUNE_SAMPLE, k), tot_sample / steps / 2, reps=1)
         torch.cuda.synchronize()
         log(f"profile run done: build {tot_build / steps / 2:.3f} ms, sample {tot_sample / steps / 2:.3f} ms")
         return
@@ -203,6 +204,7 @@ def main():
         tgbs = traffic / (samp_avg_ms * 1e-3) / 1e9
         result["roofline"]["traffic_gbs"] = round(tgbs, 1)
         result["roofline"]["traffic_frac"] = round(tgbs / HBM_PEAK_GBS, 4)
+    result["sampler_roofs"] = bench_roofs(torch, n, k, wrs.tune_get(wrs.TUNE_SAMPLE, k), samp_avg_ms)
     if not args.skip_extras:
         result["build_plus"] = bench_plus(wrs, torch, inputs, n, table)
         result["two_level"] = bench_twolevel(wrs, torch, inputs, n, table, k, out)
@@ -459,32 +461,34 @@ def bench_batched(wrs, torch, np, workloads, run_tune=True):
             "fused_hbm_frac_28B_per_item": round(28.0 * items / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def bench_served(wrs, torch, np, workloads, count=3000, inflight=2):
-    """Poisson request stream (seed 5) at a fixed rate; continuous batching
-    against one launch per request in arrival order, same trace."""
+def bench_served(wrs, torch, np, workloads, count=20000, warmup=1000, repeats=3, inflight=2,
+                 lambdas=(0.25, 0.5, 0.75, 0.9, 1.1)):
+    """Poisson request stream (seed 5): `warmup` requests, then `count`
+    measured ones, at rates lambda x the one-at-a-time capacity (the
+    completion rate of the same trace submitted at once to the one-launch-
+    per-request server), continuous batching against one launch per request
+    on the same trace, `repeats` runs each.  Latency = completion - submission
+    of the measured requests; throughput = measured requests over the span
+    from the first measured submission to the last measured completion."""
     import ctypes
     dev = torch.device("cuda:0")
-    trace = workloads.serve_trace(seed=5, count=count, rate_hz=1.0)  # times rescaled below
-    # Weights for every build request (device resident before the trace starts).
-    builds = [r for r in trace if r["op"] == "build"]
-    log(f"served: {len(trace)} requests, {len(builds)} builds")
-    # Build weights are drawn on the GPU (torch generator, seed 5): uniform is
-    # 1 - U[0,1) in FP32, power law is i^-1 under a random permutation.
+    trace = workloads.serve_trace(seed=5, count=warmup + count, rate_hz=1.0)  # times rescaled per rate
+    log(f"served: {warmup} + {count} requests")
+    # A build of n items takes the first n weights of a resident 2^24-item
+    # array of its family, drawn on the GPU (torch generator, seed 5): uniform
+    # 1 - U[0,1) in FP32, or i^-1 under a random permutation.
     g = torch.Generator(device=dev)
     g.manual_seed(5)
-    wts = []
-    for r in builds:
-        m = r["n"]
-        if r["kind"] == "uniform":
-            w = 1.0 - torch.rand(m, generator=g, device=dev, dtype=torch.float32)
-        else:
-            base = torch.arange(1, m + 1, device=dev, dtype=torch.float64).pow(-1.0).to(torch.float32)
-            w = base[torch.randperm(m, generator=g, device=dev)]
-        wts.append(w.contiguous())
+    nmax = 1 << 24
+    fam = {"uniform": (1.0 - torch.rand(nmax, generator=g, device=dev, dtype=torch.float32)).contiguous()}
+    base = torch.arange(1, nmax + 1, device=dev, dtype=torch.float64).pow(-1.0).to(torch.float32)
+    fam["power"] = base[torch.randperm(nmax, generator=g, device=dev)].contiguous()
+    del base
     max_k = max(r["k"] for r in trace if r["op"] == "sample")
     outs = [torch.empty(max_k, dtype=torch.int32, device=dev) for _ in range(8)]
     torch.cuda.synchronize()
     L = wrs.lib()
+    cs = torch.cuda.current_stream().cuda_stream  # requests are ordered behind torch's stream
 
     def run(mode, rate_hz):
         cfg = wrs.ServeConfig(64 << 30, 256, 1 if mode == "one" else 0, inflight)
@@ -492,7 +496,6 @@ def bench_served(wrs, torch, np, workloads, count=3000, inflight=2):
         assert L.wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.OK
         tid, rid = ctypes.c_uint64(), ctypes.c_uint64()
         tables, reqs = [], []
-        bi = 0
         t_start = time.perf_counter()
         scale = 1.0 / rate_hz
         for i, r in enumerate(trace):
@@ -503,72 +506,237 @@ def bench_served(wrs, torch, np, workloads, count=3000, inflight=2):
                     break
                 if t_due - now > 2e-4:
                     time.sleep((t_due - now) * 0.5)
-            if r["op"] == "build" or not tables:
-                if r["op"] != "build":
-                    continue
-                w = wts[bi]
-                bi += 1
-                rc = L.wrs_serve_submit_build(srv, w.data_ptr(), w.numel(), ctypes.byref(tid), ctypes.byref(rid))
+            if r["op"] == "build":
+                w = fam[r["kind"]]
+                rc = L.wrs_serve_submit_build(srv, w.data_ptr(), r["n"], 0, cs, ctypes.byref(tid), ctypes.byref(rid))
                 assert rc == wrs.OK
                 tables.append(tid.value)
-            else:
-                t = tables[int(r["table_pick"] * len(tables))]
+            elif tables:
+                # a resident table: one the budget has evicted is dropped and another picked
                 o = outs[i % len(outs)]
-                rc = L.wrs_serve_submit_sample(srv, t, r["k"], r["seed"], o.data_ptr(), ctypes.byref(rid))
+                rc = wrs.ENOTFOUND
+                while rc == wrs.ENOTFOUND and tables:
+                    j = int(r["table_pick"] * len(tables))
+                    rc = L.wrs_serve_submit_sample(srv, tables[j], r["k"], r["seed"], o.data_ptr(), cs,
+                                                   ctypes.byref(rid))
+                    if rc == wrs.ENOTFOUND:
+                        tables.pop(j)
+                if rc == wrs.ENOTFOUND:
+                    continue
                 assert rc == wrs.OK
-            reqs.append(rid.value)
+            else:
+                continue
+            reqs.append((i >= warmup, r["op"], r.get("n", r.get("k")), rid.value))
         st = ctypes.c_int()
-        for q in reqs:
+        failed = 0
+        for _, _, _, q in reqs:
             L.wrs_serve_wait(srv, q, ctypes.byref(st))
+            failed += st.value != wrs.OK
+        ts, td = ctypes.c_double(), ctypes.c_double()
+        lat, t0s, t1s, work = [], [], [], 0
+        for measured, op, size, q in reqs:
+            if not measured:
+                continue
+            assert L.wrs_serve_request_times(srv, q, ctypes.byref(ts), ctypes.byref(td)) == wrs.OK
+            lat.append((td.value - ts.value) * 1e6)
+            t0s.append(ts.value)
+            t1s.append(td.value)
+            work += size
         s = wrs.ServeStats()
         L.wrs_serve_stats(srv, ctypes.byref(s))
         L.wrs_serve_destroy(srv)
-        return {"requests": int(s.completed), "failed": int(s.failed), "launches": int(s.launches),
-                "p50_us": round(s.p50_us, 1), "p99_us": round(s.p99_us, 1), "max_us": round(s.max_us, 1),
-                "busy_s": round(s.busy_s, 4),
-                "req_per_s": round(s.completed / s.busy_s, 1) if s.busy_s > 0 else None,
-                "gitems_plus_gsamples_s": round((s.items_built + s.samples_drawn) / s.busy_s / 1e9, 3) if s.busy_s > 0 else None,
-                "peak_bytes": int(s.bytes_peak)}
+        span = max(t1s) - min(t0s)
+        lat = np.asarray(lat)
+        return {"p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+                "req_per_s": len(lat) / span, "gitems_plus_gsamples_s": work / span / 1e9,
+                "failed": int(failed), "launches": int(s.launches), "peak_bytes": int(s.bytes_peak)}
 
-    # Rate: 0.75 / (mean one-at-a-time service time), service time measured on
-    # the same trace issued back to back.
+    # capacity of one launch per request: the trace submitted at once
     probe = run("one", 1e9)
-    mean_service_s = probe["busy_s"] / max(1, probe["requests"])
-    rate = 0.75 / mean_service_s
-    log(f"served: mean one-at-a-time service {mean_service_s * 1e6:.1f} us -> rate {rate:.0f}/s")
-    res = {"workload": f"Poisson stream (seed 5), {count} requests, 50% builds n in [2^10,2^24], "
-                       f"50% samples k in [2^10,2^22], 64 GB budget",
-           "rate_per_s": round(rate, 1)}
-    res["continuous_batching"] = run("batch", rate)
-    res["one_launch_per_request"] = run("one", rate)
-    # Saturated: the whole trace submitted at once; completion throughput.
+    cap = probe["req_per_s"]
+    log(f"served: one-at-a-time capacity {cap:.0f} requests/s")
+    res = {"workload": f"Poisson stream (seed 5): {warmup} warm-up + {count} measured requests, 50% builds n in "
+                       f"[2^10,2^24], 50% samples k in [2^10,2^22], 64 GB budget, {inflight} batches in flight",
+           "capacity_one_at_a_time_req_per_s": round(cap, 1), "repeats": repeats,
+           "note": "a sample request draws from a table picked uniformly among the resident ones (tables the "
+                   "budget evicted, least recently used first, are dropped from the pick)", "rates": {}}
+
+    def summary(runs):
+        out = {}
+        for key in ("p50_us", "p99_us", "req_per_s", "gitems_plus_gsamples_s"):
+            v = sorted(r[key] for r in runs)
+            out[key] = round(v[len(v) // 2], 3 if key.startswith("g") else 1)
+            out[key + "_range"] = [round(v[0], 3 if key.startswith("g") else 1),
+                                   round(v[-1], 3 if key.startswith("g") else 1)]
+        out["failed"] = sum(r["failed"] for r in runs)
+        out["launches"] = runs[0]["launches"]
+        return out
+
+    for lam in lambdas:
+        rate = lam * cap
+        log(f"served: lambda {lam} ({rate:.0f}/s)")
+        per = {"rate_per_s": round(rate, 1)}
+        for mode, name in (("batch", "continuous_batching"), ("one", "one_launch_per_request")):
+            per[name] = summary([run(mode, rate) for _ in range(repeats)])
+        res["rates"][str(lam)] = per
     sat = run("batch", 1e9)
-    res["saturated"] = {"continuous_batching": {k: sat[k] for k in ("req_per_s", "gitems_plus_gsamples_s", "p50_us",
-                                                                  "p99_us", "launches")},
-                        "one_launch_per_request": {k: probe[k] for k in ("req_per_s", "gitems_plus_gsamples_s",
-                                                                         "p50_us", "p99_us", "launches")}}
+    res["saturated"] = {"continuous_batching": {k: round(v, 1) for k, v in sat.items() if k in
+                                                ("req_per_s", "p50_us", "p99_us", "launches")},
+                        "one_launch_per_request": {k: round(v, 1) for k, v in probe.items() if k in
+                                                   ("req_per_s", "p50_us", "p99_us", "launches")}}
     return res
 
 
+def bench_roofs(torch, n, k, unroll, sample_ms, reps=3):
+    """Ceilings for the sampler at its own shape (libwrs_roofs.so): the same
+    Philox-addressed 8-byte gathers from an n-entry table of 8-byte words (2 GiB
+    at n = 2^28) with coalesced 4-byte stores and no select, and the Philox
+    blocks alone (XOR-reduced, one word stored per block)."""
+    import ctypes
+    dev = torch.device("cuda:0")
+    R = ctypes.CDLL(os.path.join(ROOT, "paper_1903_00227_amd", "libwrs_roofs.so"))
+    P = ctypes.c_void_p
+    R.wrs_roof_gather.restype = ctypes.c_int
+    R.wrs_roof_gather.argtypes = [P, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, P, P]
+    R.wrs_roof_philox.restype = ctypes.c_int
+    R.wrs_roof_philox.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, P, P]
+    R.wrs_roof_blocks.restype = ctypes.c_int64
+    R.wrs_roof_blocks.argtypes = [ctypes.c_int64, ctypes.c_int]
+    log("sampler ceilings: random gathers, Philox")
+    buf = torch.zeros(n, dtype=torch.int64, device=dev)
+    out = torch.empty(k, dtype=torch.int32, device=dev)
+    red = torch.empty(R.wrs_roof_blocks(k, unroll), dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        assert fn() == 0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            assert fn() == 0
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    g_ms = timed(lambda: R.wrs_roof_gather(buf.data_ptr(), n, 2, k, unroll, out.data_ptr(), st.cuda_stream))
+    p_ms = timed(lambda: R.wrs_roof_philox(2, k, unroll, red.data_ptr(), st.cuda_stream))
+    del buf, out, red
+    return {"workload": f"k=2^{k.bit_length() - 1} draws, {unroll} per thread, table of n=2^{n.bit_length() - 1} "
+                        "8-byte words",
+            "gather_ms": round(g_ms, 3), "gather_gsamples_s": round(k / (g_ms * 1e-3) / 1e9, 2),
+            "philox_ms": round(p_ms, 3), "philox_gsamples_s": round(k / (p_ms * 1e-3) / 1e9, 2),
+            "k_sample_frac_of_gather_roof": round(g_ms / sample_ms, 4)}
+
+
+def host_info():
+    """CPU model, logical CPUs and compiler of the host the oracle is timed on."""
+    import subprocess
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cc = subprocess.run(["g++", "--version"], capture_output=True, text=True).stdout.splitlines()[0]
+    except (OSError, IndexError):
+        cc = "unknown"
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "compiler": cc}
+
+
 def bench_cpu(np, workloads):
-    """The CPU oracle on the host's cores: FP64 Vose (sequential) on the full
-    n = 2^28 uniform input, and 2^24 sequential alias queries."""
+    """The CPU oracle on the host's cores, compiled for that host with the
+    paper's flags: FP64 Vose (sequential by definition) on the full n = 2^28
+    uniform input; alias queries on that table and exponential-clock keys of
+    the n = 2^26 power-law input on one thread and on all the threads used
+    (disjoint counter ranges); the whole sequential WOR oracle at n = 2^26,
+    k = 2^20."""
+    import ctypes
+    import tempfile
+    import threading
+
     import oracle
+    info = host_info()
+    threads = max(1, min(16, os.cpu_count() or 1))  # the host's share for one GPU
+    tmp = tempfile.mkdtemp(prefix="wrs_oracle_")
+    log(f"cpu oracle: compiling with {oracle.NATIVE_FLAGS}")
+    L = oracle.native_library(os.path.join(tmp, "liboracle_native.so"))
+    P = ctypes.c_void_p
+
+    def ptr(a):
+        return a.ctypes.data_as(P)
+
+    def parallel(fn, parts):
+        ts = [threading.Thread(target=fn, args=(p,)) for p in parts]
+        t0 = time.perf_counter()
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        return time.perf_counter() - t0
+
     n = 1 << 28
     log("cpu oracle: Vose on n=2^28")
     w = workloads.uniform(n, 2)
+    t = np.empty(n, np.float32)
+    a = np.empty(n, np.int32)
     t0 = time.perf_counter()
-    t, a = oracle.vose_build(w)
+    assert L.orc_vose_build(ptr(w), n, ptr(t), ptr(a)) == 0
     dt_build = time.perf_counter() - t0
+    del w
+    # queries: 2^24 on one thread; 2^24 per thread on all threads
     ks = 1 << 24
+    out = np.empty(ks * threads, np.int32)
     t0 = time.perf_counter()
-    oracle.alias_sample(t, a, 2, 0, 0, ks)
-    dt_s = time.perf_counter() - t0
+    assert L.orc_alias_sample(ptr(t), ptr(a), n, 2, 0, 0, ks, ptr(out)) == 0
+    dt_s1 = time.perf_counter() - t0
+    errs = []
+
+    def draws(i):
+        o = out[i * ks:(i + 1) * ks]
+        errs.append(L.orc_alias_sample(ptr(t), ptr(a), n, 2, 0, i * ks, ks, ptr(o)))
+
+    dt_sT = parallel(draws, range(threads))
+    assert all(e == 0 for e in errs)
+    del t, a, out
+    # without replacement, n = 2^26 power law s = 0.5 (seed 3)
+    nw = 1 << 26
+    log("cpu oracle: WOR on n=2^26")
+    ww = workloads.power_law(nw, 0.5, 3)
+    kw = 1 << 20
+    sel = np.empty(kw, np.int32)
+    kth = ctypes.c_double()
+    t0 = time.perf_counter()
+    assert L.orc_sample_wor(ptr(ww), nw, kw, 3, 0, ptr(sel), ctypes.byref(kth)) == 0
+    dt_wor = time.perf_counter() - t0
+    keys = np.empty(nw, np.float64)
+    idx = np.arange(nw, dtype=np.int64)
+    chunk = -(-nw // threads)
+    t0 = time.perf_counter()
+    assert L.orc_wor_keys_at(ptr(ww), nw, 3, 0, ptr(idx), nw, ptr(keys)) == 0
+    dt_k1 = time.perf_counter() - t0
+    errs.clear()
+
+    def keygen(i):
+        lo, hi = i * chunk, min(nw, (i + 1) * chunk)
+        errs.append(L.orc_wor_keys_at(ptr(ww), nw, 3, 0, ptr(idx[lo:hi]), hi - lo, ptr(keys[lo:hi])))
+
+    dt_kT = parallel(keygen, range(threads))
+    assert all(e == 0 for e in errs)
     return {"value": round(n / dt_build / 1e9, 4), "unit": "Gitems/s", "cores": 1, "kind": "oracle",
-            "sample": "FP64 Vose build of the full n=2^28 uniform input (seed 2), one thread; "
-                      f"{ks} sequential alias queries on that table",
+            "sample": "FP64 Vose build of the full n=2^28 uniform input (seed 2), one thread (Vose is sequential); "
+                      f"alias queries on that table: 2^24 on one thread, 2^24 per thread on {threads} threads; "
+                      "exponential-clock keys of the n=2^26 power-law s=0.5 input (seed 3) on 1 and "
+                      f"{threads} threads; the sequential WOR oracle at n=2^26, k=2^20",
+            "host": info, "flags": oracle.NATIVE_FLAGS + " -ffp-contract=off", "threads_used": threads,
             "build_s": round(dt_build, 2),
-            "sample_gsamples_s": round(ks / dt_s / 1e9, 4)}
+            "sample_gsamples_s": {"1": round(ks / dt_s1 / 1e9, 4),
+                                  str(threads): round(ks * threads / dt_sT / 1e9, 4)},
+            "wor_keys_gitems_s": {"1": round(nw / dt_k1 / 1e9, 4), str(threads): round(nw / dt_kT / 1e9, 4)},
+            "wor_n2p26_k2p20_s": round(dt_wor, 2)}
 
 
 if __name__ == "__main__":

@@ -299,13 +299,27 @@ int wrs_tune_load(const char* path);
  * order when `one_at_a_time` is set (the baseline).
  * wrs_serve_create reserves the whole budget as one device allocation and,
  * per concurrent batch, descriptor buffers for max_batch requests (device
- * memory from the budget and pinned host memory); requests allocate nothing
- * outside the budget.  Idle tables are evicted, least recently used first, to
+ * memory from the budget and pinned host memory), plus a pinned staging arena
+ * of host_stage_bytes for builds from host weights; requests allocate nothing
+ * outside these.  Idle tables are evicted, least recently used first, to
  * admit a build.  A build that cannot be admitted while nothing runs and no
  * table is idle (the budget is held by tables that requests queued behind it
  * still need) fails with WRS_ENOMEM rather than wait for ever; so do draws
  * from its table.  A batch whose launch fails fails all its requests with
- * WRS_EDEVICE. */
+ * WRS_EDEVICE.  Every address a served request's kernels write is fixed by its
+ * sizes (table entry i < n, draw s < k), never by the weights' values.
+ *
+ * Ordering with the caller: each submit takes the caller's stream (a
+ * hipStream_t of the server's device, or NULL).  With a stream, the server
+ * records an event on it during the call, and the request's batch waits for
+ * that event on the device before it reads the request's weights or writes
+ * its outputs: everything the caller queued on that stream before the submit
+ * (producing the weights, a previous reader of the output buffer, a
+ * deallocation and reuse of the buffer's memory by a caching allocator) runs
+ * first.  With NULL there is no ordering: the caller must have completed that
+ * work already (for instance with a device synchronisation).  Completion is
+ * reported on the host (wrs_serve_poll, wrs_serve_wait); a result may be read
+ * on any stream after that. */
 #define WRS_SERVE_MAX_BATCH 4096
 #define WRS_SERVE_MAX_INFLIGHT 16
 typedef struct {
@@ -313,6 +327,8 @@ typedef struct {
     int32_t max_batch;         /* requests per batched launch, 1..WRS_SERVE_MAX_BATCH */
     int32_t one_at_a_time;     /* 0: continuous batching, 1: one launch per request, FIFO */
     int32_t inflight;          /* batches that may run concurrently, 1..WRS_SERVE_MAX_INFLIGHT */
+    int32_t pad;
+    size_t host_stage_bytes;   /* pinned staging for host weights (0: device weights only) */
 } wrs_serve_config;
 
 typedef struct {
@@ -327,16 +343,29 @@ typedef struct {
 } wrs_serve_stats_t;
 
 int wrs_serve_create(const wrs_serve_config* cfg, void** srv);
-/* Build request: d_w is a device pointer to n weights that must stay valid
- * until the request completes.  *table_id names the resident table. */
-int wrs_serve_submit_build(void* srv, const float* d_w, int64_t n, uint64_t* table_id, uint64_t* req);
+/* Build request over n weights (problem statement of Section 1; the table is
+ * wrs_alias_build's).  w_on_host = 0: w is a device pointer that must stay
+ * valid until the request completes.  w_on_host = 1: w is host memory; the
+ * call copies the n weights into the staging arena (waiting, if the arena is
+ * full, for running requests to retire; WRS_ENOMEM if 4 n bytes exceed the
+ * arena) and w is free again when it returns; the server copies them to the
+ * device on the batch's stream.  stream: see "Ordering with the caller".
+ * *table_id names the resident table. */
+int wrs_serve_submit_build(void* srv, const float* w, int64_t n, int32_t w_on_host, void* stream,
+                           uint64_t* table_id, uint64_t* req);
 /* Sample request: k draws from a resident table (seed, stream_id 0, counters
  * 0..k-1) into the device buffer d_out (k int32).  The table may still be
- * under construction; the request then runs after it. */
+ * under construction; the request then runs after it.  stream: see
+ * "Ordering with the caller". */
 int wrs_serve_submit_sample(void* srv, uint64_t table_id, int64_t k, uint64_t seed, int32_t* d_out,
-                            uint64_t* req);
+                            void* stream, uint64_t* req);
 int wrs_serve_poll(void* srv, uint64_t req, int* done, int* status);
 int wrs_serve_wait(void* srv, uint64_t req, int* status);
+/* Submission and completion times of a finished request, in seconds of the
+ * host's steady clock (the clock of wrs_serve_stats' latencies); WRS_EBUSY
+ * while it runs.  For latency statistics over a chosen part of a request
+ * stream (for instance after a warm-up). */
+int wrs_serve_request_times(void* srv, uint64_t req, double* submit_s, double* done_s);
 /* Drop a table once no pending request uses it (WRS_EBUSY otherwise). */
 int wrs_serve_release_table(void* srv, uint64_t table_id);
 /* Read a table back into host memory (n entries), e.g. to compare results. */

@@ -35,13 +35,29 @@ def build() -> None:
     subprocess.run(["sh", os.path.join(_HERE, "build.sh")], check=True)
 
 
+NATIVE_FLAGS = "-O3 -march=native"
+
+
+def native_library(path):
+    """Compile a copy of the oracle for the host it runs on (g++ with
+    NATIVE_FLAGS, as the paper's experiments compile) into `path`, and load it
+    with the same signatures.  For timing the oracle on the CPU."""
+    subprocess.run(["sh", os.path.join(_HERE, "build.sh"), os.path.abspath(path), *NATIVE_FLAGS.split()],
+                   check=True)
+    return _bind(ctypes.CDLL(os.path.abspath(path)))
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
         build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    _lib = _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
+
+
+def _bind(lib):
     P = ctypes.c_void_p
     i64, u64, u32, i32 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
     sig = {
@@ -74,7 +90,6 @@ def _load():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    _lib = lib
     return lib
 
 

@@ -39,7 +39,8 @@ class Job(ctypes.Structure):
 
 class ServeConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
-                ("one_at_a_time", ctypes.c_int32), ("inflight", ctypes.c_int32)]
+                ("one_at_a_time", ctypes.c_int32), ("inflight", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("host_stage_bytes", ctypes.c_size_t)]
 
 
 class ServeStats(ctypes.Structure):
@@ -93,13 +94,17 @@ EXPORTS = {
     "wrs_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
     "wrs_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "wrs_serve_create": (ctypes.c_int, [ctypes.POINTER(ServeConfig), ctypes.POINTER(ctypes.c_void_p)]),
-    "wrs_serve_submit_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
-                                              ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+    "wrs_serve_submit_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                              ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
+                                              ctypes.POINTER(ctypes.c_uint64)]),
     "wrs_serve_submit_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
-                                               ctypes.c_uint64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+                                               ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.POINTER(ctypes.c_uint64)]),
     "wrs_serve_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int)]),
     "wrs_serve_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
+    "wrs_serve_request_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(ctypes.c_double)]),
     "wrs_serve_release_table": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "wrs_serve_read_table": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int64]),
     "wrs_serve_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServeStats)]),

@@ -1,4 +1,5 @@
-"""Builds the HIP library libwrs.so (gfx950) in the package directory."""
+"""Builds the HIP library libwrs.so (gfx950) in the package directory, and
+libwrs_roofs.so, the benchmark's ceiling kernels (random gathers, Philox)."""
 from __future__ import annotations
 
 import glob
@@ -8,6 +9,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libwrs.so")
+ROOFS_LIB = os.path.join(HERE, "libwrs_roofs.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -20,14 +22,19 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
+def _hipcc(srcs, out, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), *sources(), "-o", tmp]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(sources(), LIB, verbose)
+    _hipcc([os.path.join(HERE, "roofs", "wrs_roofs.hip")], ROOFS_LIB, verbose)
     return LIB
 
 

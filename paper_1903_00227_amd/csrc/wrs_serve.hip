@@ -9,6 +9,13 @@
 // and keeps up to `inflight` such batches running on separate streams while it
 // forms the next (continuous batching).  With one_at_a_time = 1 the same loop
 // issues one request per launch, strictly in arrival order, as the baseline.
+//
+// Ordering with the caller: a request submitted with the caller's stream
+// records an event on that stream at submission, and its batch waits for the
+// event on the device before it reads the request's inputs or writes its
+// outputs.  Host weights are copied at submission into a pinned staging arena
+// (the caller's buffer is free again when the call returns) and from there
+// into pool memory on the batch's stream.
 #include <stdio.h>
 #include <string.h>
 
@@ -81,6 +88,9 @@ struct Request {
     int64_t k = 0;
     uint64_t seed = 0;
     int32_t* d_out = nullptr;
+    hipEvent_t after = nullptr;  // recorded on the caller's stream at submission
+    float* h_stage = nullptr;    // build from host weights: their copy in the staging arena
+    size_t stage_bytes = 0;
     double t_submit = 0, t_done = 0;
     int status = WRS_OK;
     bool done = false;
@@ -100,6 +110,9 @@ struct Server {
     wrs_serve_config cfg;
     int device = 0;
     Pool pool;
+    char* h_arena = nullptr;     // pinned staging for host weights (cfg.host_stage_bytes)
+    FirstFit stage;
+    std::vector<hipEvent_t> free_events;  // recycled submission events
     std::mutex mu;
     std::condition_variable cv, cv_done;
     std::deque<Request*> queue;
@@ -135,7 +148,14 @@ static size_t status_bytes(int njobs) { return ((size_t)sizeof(int32_t) * njobs 
 // build and sample job tables (nb + ns <= maxb) and the build statuses.
 static size_t slot_bytes(int maxb) { return 2 * descriptor_bytes(maxb) + status_bytes(maxb); }
 
+// A request is finished once its batch has run, or when it fails before it
+// is issued: the event it waited for, and the host copy of its weights, are
+// free again.
 static void finish_request(Server& S, Request* r, int status, double t) {
+    if (r->after) S.free_events.push_back(r->after);
+    r->after = nullptr;
+    S.stage.release(r->h_stage, r->stage_bytes);
+    r->h_stage = nullptr;
     r->status = status;
     r->done = true;
     r->t_done = t;
@@ -216,7 +236,8 @@ static bool issue(Server& S) {
         Request* r = S.queue.front();
         Table* tb = S.tables[r->table_id].get();
         if (r->op == OP_BUILD) {
-            const size_t wsb = build_ws_bytes(tb->n) + 256;
+            // a build from host weights also holds their device copy until it retires
+            const size_t wsb = build_ws_bytes(tb->n) + 256 + (r->h_stage ? r->stage_bytes : 0);
             const size_t need = tb->table_bytes + wsb + 256;
             void* ws = nullptr;
             bool placed = make_room(S, need);
@@ -266,6 +287,10 @@ static bool issue(Server& S) {
     }
     if (take.empty()) return false;
     hipStream_t st = S.streams[slot];
+    // nothing of the batch touches a request's inputs or outputs before the
+    // work the caller queued on its stream ahead of the submission has run
+    for (Request* r : take)
+        if (r->after) (void)hipStreamWaitEvent(st, r->after, 0);
     // descriptors: builds first, then samples, each its own job table
     const int nb = (int)bld.size(), ns = (int)smp.size();
     // bb + sb + status_bytes(nb) <= slot_bytes(max batch): the slot's buffers hold it
@@ -286,10 +311,18 @@ static bool issue(Server& S) {
         for (int j = 0; j < nb; ++j) {
             Table* tb = S.tables[bld[j]->table_id].get();
             memset(&d[j], 0, sizeof(JobDesc));
+            char* wsp = (char*)scratch[wsi++].first;
             d[j].w = tb->d_w;
+            if (bld[j]->h_stage) {
+                // host weights: copied behind the workspace, then built from there
+                float* dw = (float*)(wsp + ((build_ws_bytes(tb->n) + 255) & ~(size_t)255));
+                ok = ok && hipMemcpyAsync(dw, bld[j]->h_stage, bld[j]->stage_bytes, hipMemcpyHostToDevice, st) ==
+                               hipSuccess;
+                d[j].w = dw;
+            }
             d[j].table = tb->d_table;
             set_sample_job(d[j], 0, 1);
-            build_ws_layout(d[j], scratch[wsi++].first, tb->n);
+            build_ws_layout(d[j], wsp, tb->n);
             d[j].sc = tb->sc;
             int64_t b[PH_COUNT];
             phase_blocks(d[j], b);
@@ -404,6 +437,32 @@ static void release_slots(Server* S) {
         if (p) (void)hipHostFree(p);
     S->streams.clear();
     S->staging.clear();
+    for (auto e : S->free_events) (void)hipEventDestroy(e);
+    S->free_events.clear();
+    if (S->h_arena) (void)hipHostFree(S->h_arena);
+    S->h_arena = nullptr;
+}
+
+// An event recorded on the caller's stream now (lock held); nullptr and
+// WRS_OK when no stream is given.
+static int submission_event(Server& S, void* stream, hipEvent_t* out) {
+    *out = nullptr;
+    if (!stream) return WRS_OK;
+    hipEvent_t e = nullptr;
+    if (!S.free_events.empty()) {
+        e = S.free_events.back();
+        S.free_events.pop_back();
+    } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        set_error("wrs_serve_submit: event creation failed");
+        return WRS_EDEVICE;
+    }
+    if (hipEventRecord(e, (hipStream_t)stream) != hipSuccess) {
+        S.free_events.push_back(e);
+        set_error("wrs_serve_submit: cannot record on the caller's stream");
+        return WRS_EDEVICE;
+    }
+    *out = e;
+    return WRS_OK;
 }
 
 extern "C" int wrs_serve_create(const wrs_serve_config* cfg, void** srv) {
@@ -421,6 +480,14 @@ extern "C" int wrs_serve_create(const wrs_serve_config* cfg, void** srv) {
         delete S;
         set_error("wrs_serve_create: cannot reserve %zu bytes", cfg->hbm_budget_bytes);
         return WRS_ENOMEM;
+    }
+    if (cfg->host_stage_bytes > 0) {
+        if (hipHostMalloc((void**)&S->h_arena, cfg->host_stage_bytes) != hipSuccess) {
+            delete S;
+            set_error("wrs_serve_create: cannot reserve %zu bytes of pinned staging", cfg->host_stage_bytes);
+            return WRS_ENOMEM;
+        }
+        S->stage.reset(S->h_arena, cfg->host_stage_bytes);
     }
     const size_t sbytes = slot_bytes(S->maxb);
     for (int i = 0; i < S->cfg.inflight; ++i) {
@@ -451,23 +518,49 @@ extern "C" int wrs_serve_create(const wrs_serve_config* cfg, void** srv) {
     return WRS_OK;
 }
 
-extern "C" int wrs_serve_submit_build(void* srv, const float* d_w, int64_t n, uint64_t* table_id, uint64_t* req) {
+extern "C" int wrs_serve_submit_build(void* srv, const float* w, int64_t n, int32_t w_on_host, void* stream,
+                                      uint64_t* table_id, uint64_t* req) {
     auto* S = (Server*)srv;
-    if (!S || !d_w || !table_id || !req || n < 1 || n > 2147483647LL) { set_error("wrs_serve_submit_build: bad arguments"); return WRS_EINVAL; }
-    const size_t need = (size_t)n * sizeof(wrs_entry) + build_ws_bytes(n) + 1024;
+    if (!S || !w || !table_id || !req || n < 1 || n > 2147483647LL || (w_on_host != 0 && w_on_host != 1)) {
+        set_error("wrs_serve_submit_build: bad arguments");
+        return WRS_EINVAL;
+    }
+    const size_t wbytes = (size_t)n * sizeof(float);
+    if (w_on_host && wbytes > S->stage.size()) {
+        set_error("wrs_serve_submit_build: %zu bytes of host weights exceed the staging arena", wbytes);
+        return WRS_ENOMEM;
+    }
+    const size_t need = (size_t)n * sizeof(wrs_entry) + build_ws_bytes(n) + 1024 + (w_on_host ? wbytes : 0);
     const size_t avail = S->cfg.hbm_budget_bytes > S->reserved ? S->cfg.hbm_budget_bytes - S->reserved : 0;
     if (need > avail) { set_error("wrs_serve_submit_build: request exceeds the HBM budget"); return WRS_ENOMEM; }
+    float* stage = nullptr;
+    if (w_on_host) {
+        // room in the staging arena, waiting for running requests to retire
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv_done.wait(lk, [&] { return (stage = (float*)S->stage.alloc(wbytes)) != nullptr || S->stop; });
+        if (!stage) { set_error("wrs_serve_submit_build: server stopping"); return WRS_EINVAL; }
+        lk.unlock();
+        memcpy(stage, w, wbytes);  // the caller's buffer is free when the call returns
+    }
     std::lock_guard<std::mutex> g(S->mu);
+    auto r = std::make_unique<Request>();
+    const int er = submission_event(*S, stream, &r->after);
+    if (er != WRS_OK) {
+        S->stage.release(stage, wbytes);
+        S->cv_done.notify_all();
+        return er;
+    }
     auto t = std::make_unique<Table>();
     t->id = S->next_id++;
     t->n = n;
-    t->d_w = d_w;
+    t->d_w = w_on_host ? nullptr : w;
     t->table_bytes = (size_t)n * sizeof(wrs_entry);
     t->refs = 1;
-    auto r = std::make_unique<Request>();
     r->id = S->next_id++;
     r->op = OP_BUILD;
     r->table_id = t->id;
+    r->h_stage = stage;
+    r->stage_bytes = stage ? wbytes : 0;
     r->t_submit = now_s();
     if (S->t_first < 0) S->t_first = r->t_submit;
     *table_id = t->id;
@@ -483,14 +576,16 @@ extern "C" int wrs_serve_submit_build(void* srv, const float* d_w, int64_t n, ui
 }
 
 extern "C" int wrs_serve_submit_sample(void* srv, uint64_t table_id, int64_t k, uint64_t seed, int32_t* d_out,
-                                       uint64_t* req) {
+                                       void* stream, uint64_t* req) {
     auto* S = (Server*)srv;
     if (!S || !req || k < 1 || !d_out) { set_error("wrs_serve_submit_sample: bad arguments"); return WRS_EINVAL; }
     std::lock_guard<std::mutex> g(S->mu);
     auto it = S->tables.find(table_id);
     if (it == S->tables.end()) { set_error("wrs_serve_submit_sample: unknown table %llu", (unsigned long long)table_id); return WRS_ENOTFOUND; }
-    it->second->refs++;
     auto r = std::make_unique<Request>();
+    const int er = submission_event(*S, stream, &r->after);
+    if (er != WRS_OK) return er;
+    it->second->refs++;
     r->id = S->next_id++;
     r->op = OP_SAMPLE;
     r->table_id = table_id;
@@ -517,6 +612,18 @@ extern "C" int wrs_serve_poll(void* srv, uint64_t req, int* done, int* status) {
     if (it == S->reqs.end()) return WRS_ENOTFOUND;
     *done = it->second->done;
     *status = it->second->status;
+    return WRS_OK;
+}
+
+extern "C" int wrs_serve_request_times(void* srv, uint64_t req, double* submit_s, double* done_s) {
+    auto* S = (Server*)srv;
+    if (!S || !submit_s || !done_s) return WRS_EINVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(req);
+    if (it == S->reqs.end()) return WRS_ENOTFOUND;
+    if (!it->second->done) return WRS_EBUSY;
+    *submit_s = it->second->t_submit;
+    *done_s = it->second->t_done;
     return WRS_OK;
 }
 
@@ -599,6 +706,7 @@ extern "C" int wrs_serve_destroy(void* srv) {
         std::lock_guard<std::mutex> g(S->mu);
         S->stop = true;
         S->cv.notify_all();
+        S->cv_done.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
     for (auto& kv : S->tables)

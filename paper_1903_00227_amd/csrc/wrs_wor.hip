@@ -17,9 +17,14 @@
 //                 takes more than a few hundred atomics; k_wor_shards turns
 //                 the 64 counts into a prefix table, and later kernels address
 //                 candidate c through it.
-//   k_wor_hist / k_wor_find   radix-style select of the k-th smallest key over
-//                 the candidates: linear bins on the key, two levels of 16384
-//                 bins, until at most 8192 candidates share the target bin
+//   k_wor_hist / k_wor_find   select of the k-th smallest key over the
+//                 candidates, by levels of 16384 bins until at most 8192
+//                 candidates share the target bin: two levels of linear bins on
+//                 the key (enough when the candidates are the threshold pass's),
+//                 then radix levels on the key's FP64 bit pattern, 14 bits at a
+//                 time from the top (a non-negative double's bit pattern orders
+//                 like its value), which resolve any spread of keys, such as
+//                 the fallback pass's, unless more than 8192 keys are equal
 //   k_wor_gather / k_wor_final  sort that bin in LDS, take the exact k-th (key, idx)
 //   k_wor_mark    set one bit per selected item in an n-bit map
 //   k_wor_popc / k_wor_popscan / k_wor_compact   emit the set bits in index order
@@ -32,7 +37,8 @@ namespace wrs {
 constexpr int WOR_TPB = 256;
 constexpr int WOR_IPT = 8;                       // items per thread in the filter
 constexpr int WOR_NB = 16384;                    // bins per select level
-constexpr int WOR_NLEV = 2;                      // select levels
+constexpr int WOR_NLIN = 2;                      // linear select levels
+constexpr int WOR_NLEV = WOR_NLIN + 5;           // then radix levels: bit shifts 50, 36, 22, 8, 0
 constexpr int WOR_SMALL = 8192;                  // final in-LDS sort capacity
 constexpr int WOR_TAU_M = 4096;                  // subsample size for tau
 constexpr int WOR_WPB = WOR_TPB * 16;            // bitmap words per compaction block
@@ -54,6 +60,7 @@ struct WorScalars {
     int64_t k;
     int64_t rank;            // remaining 1-based rank inside the current bin
     int32_t level_bin[WOR_NLEV];
+    uint64_t radix_prefix;   // radix levels: the chosen digits so far (bits above the level's shift)
     int32_t nlev;            // levels used; set when resolved
     int32_t resolved;
     uint32_t small_count;
@@ -370,10 +377,29 @@ __device__ __forceinline__ int wor_bin(double key, double lo, double scale) {
     return (int)fmin(fmax(b, 0.0), (double)(WOR_NB - 1));
 }
 
+// Radix level l >= WOR_NLIN: the 14-bit digit of the key's bit pattern at this
+// shift (the last level takes the 8 lowest bits).
+__device__ __forceinline__ int wor_shift(int l) { return max(0, 50 - 14 * (l - WOR_NLIN)); }
+__device__ __forceinline__ int wor_digit(double key, int l) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(key);
+    return (int)(l == WOR_NLEV - 1 ? (bits & 0xFFu) : ((bits >> wor_shift(l)) & (uint64_t)(WOR_NB - 1)));
+}
+
+// Bin of a key at level l (linear, or radix).
+__device__ __forceinline__ int wor_level_bin(const WorScalars* S, double key, int l) {
+    return l < WOR_NLIN ? wor_bin(key, S->level_lo[l], S->level_scale[l]) : wor_digit(key, l);
+}
+
 // Does candidate key fall into the chosen bins of levels [0, upto)?
 __device__ __forceinline__ bool wor_in_set(const WorScalars* S, double key, int upto) {
-    for (int l = 0; l < upto; ++l)
+    for (int l = 0; l < min(upto, WOR_NLIN); ++l)
         if (wor_bin(key, S->level_lo[l], S->level_scale[l]) != S->level_bin[l]) return false;
+    if (upto > WOR_NLIN) {
+        // radix levels [WOR_NLIN, upto): the bits above the last chosen level's shift
+        const uint64_t bits = (uint64_t)__double_as_longlong(key);
+        const int sh = wor_shift(upto - 1);
+        if ((bits >> sh) != S->radix_prefix) return false;
+    }
     return true;
 }
 
@@ -394,15 +420,19 @@ __global__ __launch_bounds__(WOR_CAND_TPB) void k_wor_hist(WorArgs A, int level)
             S->level_lo[0] = lo;
             S->level_scale[0] = scale;
         }
-    } else {
+    } else if (level < WOR_NLIN) {
         lo = S->level_lo[level];
         scale = S->level_scale[level];
+    } else {
+        lo = 0.0;
+        scale = 1.0;
     }
     for (int i = threadIdx.x; i < WOR_NB; i += WOR_CAND_TPB) h[i] = 0;
     __syncthreads();
     for (int64_t c = (int64_t)blockIdx.x * WOR_CAND_TPB + threadIdx.x; c < nc; c += (int64_t)gridDim.x * WOR_CAND_TPB) {
         const double key = A.ckey[cand_slot(P, A.scap, (uint32_t)c)];
-        if (level == 0 || wor_in_set(S, key, level)) atomicAdd(&h[wor_bin(key, lo, scale)], 1u);
+        if (level == 0 || wor_in_set(S, key, level))
+            atomicAdd(&h[level < WOR_NLIN ? wor_bin(key, lo, scale) : wor_digit(key, level)], 1u);
     }
     __syncthreads();
     uint32_t* g = A.hist + (size_t)level * WOR_NB;
@@ -442,16 +472,22 @@ __global__ __launch_bounds__(1024) void k_wor_find(WorArgs A, int level) {
         const uint32_t cnt = g[b];
         S->rank = rank - cum;
         S->level_bin[level] = b;
+        if (level >= WOR_NLIN)  // the digits chosen so far: the bits above this level's shift
+            S->radix_prefix = level == WOR_NLIN       ? (uint64_t)b
+                              : level == WOR_NLEV - 1 ? (S->radix_prefix << 8) | (uint64_t)b
+                                                      : (S->radix_prefix << 14) | (uint64_t)b;
         if (cnt <= (uint32_t)WOR_SMALL) {
             S->resolved = 1;
             S->nlev = level + 1;
             S->small_count = 0;
-        } else if (level + 1 < WOR_NLEV) {
+        } else if (level + 1 < WOR_NLIN) {
             const double lo = S->level_lo[level], sc = S->level_scale[level];
             S->level_lo[level + 1] = lo + (double)b / sc;
             S->level_scale[level + 1] = sc * (double)WOR_NB;
+        } else if (level + 1 < WOR_NLEV) {
+            // the next level refines the chosen bin (radix levels keep radix_prefix)
         } else {
-            S->status = WRS_EDEVICE;  // more than WOR_SMALL keys tie at the boundary
+            S->status = WRS_EDEVICE;  // more than WOR_SMALL keys equal at the boundary
         }
     }
 }

@@ -11,6 +11,12 @@ def say(*a):
     sys.stdout.flush()
 
 
+def cur_stream():
+    """Handle of torch's current HIP stream (the stream the serve submits order against)."""
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
 def torch_dev():
     import torch
     return torch.device("cuda:0")
@@ -74,3 +80,43 @@ def family(name, n, seed):
         w[rng.integers(0, n, max(1, n // 50))] = np.float32(1e-3)
         return w
     raise ValueError(name)
+
+
+def t_tolerance(n, t_ref):
+    """Threshold bar against the exact sweep: 1 ulp, plus for a heavy bucket
+    (TILE/2 + 1) merge-key units of at most 2^(floor(log2 n) - 60) bucket each."""
+    unit = 2.0 ** (int(n).bit_length() - 1 - 60)
+    ulp = np.spacing(np.abs(t_ref).astype(np.float32)).astype(np.float64)
+    return ulp + 513 * unit
+
+
+def check_against_sweep(orc, w, t, a):
+    """Aliases equal to the exact sequential sweep (Algorithm 2), thresholds
+    within t_tolerance (lights within 1 ulp), every positive item's mass within
+    1e-6 relative of n w_i / W, zero-weight items with mass 0."""
+    t_ref, a_ref = orc.sweep_build(w)
+    bad = np.nonzero(a != a_ref)[0]
+    assert bad.size == 0, f"{bad.size} alias mismatches, first at {bad[:5]}: gpu {a[bad[:5]]} ref {a_ref[bad[:5]]}"
+    dt = np.abs(t.astype(np.float64) - t_ref.astype(np.float64))
+    tol = t_tolerance(w.size, t_ref)
+    assert np.all(dt <= tol), f"threshold off by {dt.max()} at {np.argmax(dt - tol)}"
+    light = w.astype(np.float64) * w.size <= w.astype(np.float64).sum() * (1 - 1e-12)
+    assert ulp_diff(t[light], t_ref[light]).max(initial=0) <= 1
+    check_masses(orc, w, t, a)
+
+
+def check_masses(orc, w, t, a):
+    """Every positive item's reconstructed mass within 1e-6 relative of
+    n w_i / W, zero-weight items with mass 0, t in [0, 1], aliases in [0, n)."""
+    assert np.all((t >= 0) & (t <= 1)) and np.all((a >= 0) & (a < w.size))
+    mass, err = orc.reconstruct(w, t, a)
+    pos = w > 0
+    if pos.any():
+        assert err[pos].max() <= 1e-6
+    assert np.all(mass[~pos] == 0)
+
+
+def split_table(tab):
+    """(t, alias) arrays of a table read back as an (n, 2) int32 array."""
+    tab = np.asarray(tab)
+    return tab[:, 0].copy().view(np.float32), tab[:, 1].copy()

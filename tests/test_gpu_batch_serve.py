@@ -1,10 +1,12 @@
 """Batched and served operation: every job's or request's results must be
-bit-identical to the single-call results for the same weights, seed and stream."""
+bit-identical to the single-call results for the same weights, seed and stream;
+served builds from host weights, and requests submitted while their inputs are
+still being produced on the caller's stream, must equal the oracle."""
 import numpy as np
 import pytest
 
 import workloads
-from gpu_common import say
+from gpu_common import check_against_sweep, cur_stream, say, split_table
 
 pytestmark = pytest.mark.gpu
 
@@ -103,26 +105,31 @@ def test_batch_reports_bad_job(wrs):
 
 
 def run_server(wrs, reqs, weights, one_at_a_time, budget=8 << 30):
-    """Submit (op, ...) requests, wait for all; return tables and outputs."""
+    """Submit (op, ...) requests, wait for all; return tables and outputs.
+    Outputs are allocated and filled before the server starts; every submit
+    also orders its request behind torch's stream."""
     import ctypes
     import torch
+    outs = [torch.full((r[2],), -1, dtype=torch.int32, device="cuda:0") for r in reqs if r[0] == "sample"]
+    torch.cuda.synchronize()
     cfg = wrs.ServeConfig(budget, 64, 1 if one_at_a_time else 0, 2)
     srv = ctypes.c_void_p()
     assert wrs.lib().wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.OK
     tid, rid = ctypes.c_uint64(), ctypes.c_uint64()
-    table_ids, req_ids, outs = [], [], []
+    table_ids, req_ids = [], []
+    si = 0
     for r in reqs:
         if r[0] == "build":
             w = weights[r[1]]
-            assert wrs.lib().wrs_serve_submit_build(srv, w.data_ptr(), w.numel(), ctypes.byref(tid),
+            assert wrs.lib().wrs_serve_submit_build(srv, w.data_ptr(), w.numel(), 0, cur_stream(), ctypes.byref(tid),
                                                     ctypes.byref(rid)) == wrs.OK
             table_ids.append(tid.value)
         else:
             _, ti, k, seed = r
-            out = torch.full((k,), -1, dtype=torch.int32, device="cuda:0")
-            assert wrs.lib().wrs_serve_submit_sample(srv, table_ids[ti], k, seed, out.data_ptr(),
+            out = outs[si]
+            si += 1
+            assert wrs.lib().wrs_serve_submit_sample(srv, table_ids[ti], k, seed, out.data_ptr(), cur_stream(),
                                                      ctypes.byref(rid)) == wrs.OK
-            outs.append(out)
         req_ids.append(rid.value)
     st = ctypes.c_int()
     for q in req_ids:
@@ -187,15 +194,15 @@ def test_serve_failures_are_contained(wrs):
         bad[1234] = float("nan")
         good = torch.from_numpy(workloads.power_law(70000, 1.0, 9)).to("cuda:0")
         say("serve: bad build, good build, draws from both")
-        assert L.wrs_serve_submit_build(srv, bad.data_ptr(), bad.numel(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
+        assert L.wrs_serve_submit_build(srv, bad.data_ptr(), bad.numel(), 0, cur_stream(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
         t_bad, r_bad = tid.value, rid.value
-        assert L.wrs_serve_submit_build(srv, good.data_ptr(), good.numel(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
+        assert L.wrs_serve_submit_build(srv, good.data_ptr(), good.numel(), 0, cur_stream(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
         t_good, r_good = tid.value, rid.value
         o_bad = torch.full((1000,), -1, dtype=torch.int32, device="cuda:0")
         o_good = torch.full((30000,), -1, dtype=torch.int32, device="cuda:0")
-        assert L.wrs_serve_submit_sample(srv, t_bad, 1000, 3, o_bad.data_ptr(), ctypes.byref(rid)) == wrs.OK
+        assert L.wrs_serve_submit_sample(srv, t_bad, 1000, 3, o_bad.data_ptr(), cur_stream(), ctypes.byref(rid)) == wrs.OK
         r_sbad = rid.value
-        assert L.wrs_serve_submit_sample(srv, t_good, 30000, 4, o_good.data_ptr(), ctypes.byref(rid)) == wrs.OK
+        assert L.wrs_serve_submit_sample(srv, t_good, 30000, 4, o_good.data_ptr(), cur_stream(), ctypes.byref(rid)) == wrs.OK
         r_sgood = rid.value
         for r, want in ((r_bad, wrs.EDOMAIN), (r_good, wrs.OK), (r_sbad, wrs.EDOMAIN), (r_sgood, wrs.OK)):
             assert L.wrs_serve_wait(srv, r, ctypes.byref(st)) == wrs.OK
@@ -205,10 +212,10 @@ def test_serve_failures_are_contained(wrs):
         assert bool((o_bad == -1).all())  # nothing drawn from a failed table
         # refused at submission
         huge = torch.empty(1, dtype=torch.float32, device="cuda:0")
-        assert L.wrs_serve_submit_build(srv, huge.data_ptr(), 1 << 28, ctypes.byref(tid), ctypes.byref(rid)) == wrs.ENOMEM
-        assert L.wrs_serve_submit_sample(srv, 987654321, 10, 1, o_bad.data_ptr(), ctypes.byref(rid)) == wrs.ENOTFOUND
+        assert L.wrs_serve_submit_build(srv, huge.data_ptr(), 1 << 28, 0, cur_stream(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.ENOMEM
+        assert L.wrs_serve_submit_sample(srv, 987654321, 10, 1, o_bad.data_ptr(), cur_stream(), ctypes.byref(rid)) == wrs.ENOTFOUND
         assert L.wrs_serve_release_table(srv, t_good) == wrs.OK
-        assert L.wrs_serve_submit_sample(srv, t_good, 10, 1, o_bad.data_ptr(), ctypes.byref(rid)) == wrs.ENOTFOUND
+        assert L.wrs_serve_submit_sample(srv, t_good, 10, 1, o_bad.data_ptr(), cur_stream(), ctypes.byref(rid)) == wrs.ENOTFOUND
         s = wrs.ServeStats()
         assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
         assert s.completed == 4 and s.failed == 2
@@ -236,11 +243,11 @@ def test_serve_evicts_idle_tables_within_budget(wrs):
             w = torch.from_numpy(workloads.uniform(1 << 20, 60 + i)).to("cuda:0")
             ws_.append(w)
             say("serve under a tight budget: build", i)
-            assert L.wrs_serve_submit_build(srv, w.data_ptr(), w.numel(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
+            assert L.wrs_serve_submit_build(srv, w.data_ptr(), w.numel(), 0, cur_stream(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
             tids.append(tid.value)
             assert L.wrs_serve_wait(srv, rid.value, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
         out = torch.full((50000,), -1, dtype=torch.int32, device="cuda:0")
-        assert L.wrs_serve_submit_sample(srv, tids[-1], 50000, 7, out.data_ptr(), ctypes.byref(rid)) == wrs.OK
+        assert L.wrs_serve_submit_sample(srv, tids[-1], 50000, 7, out.data_ptr(), cur_stream(), ctypes.byref(rid)) == wrs.OK
         assert L.wrs_serve_wait(srv, rid.value, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
         _, smp = single(wrs, ws_[-1], 1 << 20, 50000, 7, 0)
         assert np.array_equal(out.cpu().numpy(), smp)
@@ -248,7 +255,7 @@ def test_serve_evicts_idle_tables_within_budget(wrs):
         assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
         assert s.bytes_peak <= budget and s.tables_resident < 6 and s.failed == 0
         # the oldest table went first
-        assert L.wrs_serve_submit_sample(srv, tids[0], 10, 1, out.data_ptr(), ctypes.byref(rid)) == wrs.ENOTFOUND
+        assert L.wrs_serve_submit_sample(srv, tids[0], 10, 1, out.data_ptr(), cur_stream(), ctypes.byref(rid)) == wrs.ENOTFOUND
     finally:
         L.wrs_serve_destroy(srv)
 
@@ -276,7 +283,7 @@ def test_serve_unadmittable_build_fails_instead_of_waiting(wrs):
         tids = []
         for i in range(3):
             say("serve: resident table", i)
-            assert L.wrs_serve_submit_build(srv, w[i].data_ptr(), n, ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
+            assert L.wrs_serve_submit_build(srv, w[i].data_ptr(), n, 0, cur_stream(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
             tids.append(tid.value)
             assert L.wrs_serve_wait(srv, rid.value, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
         s = wrs.ServeStats()
@@ -285,19 +292,19 @@ def test_serve_unadmittable_build_fails_instead_of_waiting(wrs):
         kx = 1 << 30
         out_x = torch.empty(kx, dtype=torch.int32, device="cuda:0")
         say("serve: a long draw in the only slot")
-        assert L.wrs_serve_submit_sample(srv, tids[2], kx, 9, out_x.data_ptr(), ctypes.byref(rid)) == wrs.OK
+        assert L.wrs_serve_submit_sample(srv, tids[2], kx, 9, out_x.data_ptr(), cur_stream(), ctypes.byref(rid)) == wrs.OK
         r_x = rid.value
         t0 = time.time()
         while s.launches == launches:
             assert time.time() - t0 < 10, "the long draw was never issued"
             assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
         # queued behind it: a build that needs a fourth table, then draws from all three
-        assert L.wrs_serve_submit_build(srv, w[3].data_ptr(), n, ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
+        assert L.wrs_serve_submit_build(srv, w[3].data_ptr(), n, 0, cur_stream(), ctypes.byref(tid), ctypes.byref(rid)) == wrs.OK
         t_c, r_c = tid.value, rid.value
         outs, r_s = [], []
         for i in range(3):
             o = torch.full((5000,), -1, dtype=torch.int32, device="cuda:0")
-            assert L.wrs_serve_submit_sample(srv, tids[i], 5000, 20 + i, o.data_ptr(), ctypes.byref(rid)) == wrs.OK
+            assert L.wrs_serve_submit_sample(srv, tids[i], 5000, 20 + i, o.data_ptr(), cur_stream(), ctypes.byref(rid)) == wrs.OK
             outs.append(o)
             r_s.append(rid.value)
         assert L.wrs_serve_poll(srv, r_x, ctypes.byref(done), ctypes.byref(st)) == wrs.OK
@@ -313,9 +320,117 @@ def test_serve_unadmittable_build_fails_instead_of_waiting(wrs):
         assert np.array_equal(out_x[: 1 << 16].cpu().numpy(), smp)
         # a draw from the failed table fails at once (nothing is launched for it)
         o = torch.full((10,), -1, dtype=torch.int32, device="cuda:0")
-        assert L.wrs_serve_submit_sample(srv, t_c, 10, 1, o.data_ptr(), ctypes.byref(rid)) == wrs.OK
+        assert L.wrs_serve_submit_sample(srv, t_c, 10, 1, o.data_ptr(), cur_stream(), ctypes.byref(rid)) == wrs.OK
         assert L.wrs_serve_wait(srv, rid.value, ctypes.byref(st)) == wrs.OK and st.value == wrs.ENOMEM
         assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
         assert s.failed == 2 and s.bytes_peak <= budget
+    finally:
+        L.wrs_serve_destroy(srv)
+
+
+def test_serve_host_weights(wrs, orc):
+    """Builds from host memory: the weights are copied into the pinned staging
+    arena at submission (the caller's array is overwritten right after), the
+    arena holds fewer builds than are submitted (submission waits for retired
+    requests), and every table and draw equals the oracle's.  A build larger
+    than the arena, and host weights without an arena, are refused."""
+    import ctypes
+    import torch
+    L = wrs.lib()
+    n = 1 << 20
+    sizes = [n, n + 777, 3000, n, 70001, n]
+    fams = ["uniform", "power1", "uniform", "power1", "dominant", "uniform"]
+    from gpu_common import family
+    ws_np = [family(f, m, 90 + i) for i, (m, f) in enumerate(zip(sizes, fams))]
+    outs = [torch.full((40000,), -1, dtype=torch.int32, device="cuda:0") for _ in sizes]
+    torch.cuda.synchronize()
+    cfg = wrs.ServeConfig(1 << 30, 8, 0, 2, 0, 9 << 20)  # room for two of the largest builds
+    srv = ctypes.c_void_p()
+    assert L.wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.OK
+    try:
+        tid, rid, st = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int()
+        tids, rids = [], []
+        for i, w in enumerate(ws_np):
+            buf = w.copy()
+            say("serve: host weights, build", i, "n", w.size)
+            assert L.wrs_serve_submit_build(srv, buf.ctypes.data, buf.size, 1, None, ctypes.byref(tid),
+                                            ctypes.byref(rid)) == wrs.OK
+            buf[:] = np.float32(np.nan)  # the call has copied them
+            tids.append(tid.value)
+            rids.append(rid.value)
+            assert L.wrs_serve_submit_sample(srv, tid.value, 40000, 5 + i, outs[i].data_ptr(), cur_stream(),
+                                             ctypes.byref(rid)) == wrs.OK
+            rids.append(rid.value)
+        for r in rids:
+            assert L.wrs_serve_wait(srv, r, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
+        for i, w in enumerate(ws_np):
+            h = np.empty((w.size, 2), np.int32)
+            assert L.wrs_serve_read_table(srv, tids[i], h.ctypes.data, w.size) == wrs.OK
+            t, a = split_table(h)
+            check_against_sweep(orc, w, t, a)
+            assert np.array_equal(outs[i].cpu().numpy(), orc.alias_sample(t, a, 5 + i, 0, 0, 40000))
+        big = np.ones((10 << 20) // 4, np.float32)
+        assert L.wrs_serve_submit_build(srv, big.ctypes.data, big.size, 1, None, ctypes.byref(tid),
+                                        ctypes.byref(rid)) == wrs.ENOMEM
+        assert L.wrs_serve_submit_build(srv, big.ctypes.data, big.size, 2, None, ctypes.byref(tid),
+                                        ctypes.byref(rid)) == wrs.EINVAL
+    finally:
+        L.wrs_serve_destroy(srv)
+    cfg = wrs.ServeConfig(1 << 30, 8, 0, 2)
+    assert L.wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.OK
+    try:
+        small = np.ones(100, np.float32)
+        assert L.wrs_serve_submit_build(srv, small.ctypes.data, 100, 1, None, ctypes.byref(tid),
+                                        ctypes.byref(rid)) == wrs.ENOMEM
+    finally:
+        L.wrs_serve_destroy(srv)
+
+
+def test_serve_orders_behind_the_callers_stream(wrs, orc):
+    """Weights still being produced, and output buffers still being filled, on
+    torch's stream when the requests are submitted: the batches wait for that
+    work, so every table and draw equals the oracle's."""
+    import ctypes
+    import torch
+    L = wrs.lib()
+    cfg = wrs.ServeConfig(1 << 30, 16, 0, 2)
+    srv = ctypes.c_void_p()
+    assert L.wrs_serve_create(ctypes.byref(cfg), ctypes.byref(srv)) == wrs.OK
+    try:
+        tid, rid, st = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int()
+        wanted, dev_w, outs, tids, rids = [], [], [], [], []
+        for i in range(6):
+            m = (1 << 18) + 1000 * i
+            w_np = workloads.power_law(m, 1.0, 200 + i) if i % 2 else workloads.uniform(m, 200 + i)
+            src = torch.from_numpy(w_np).to("cuda:0")
+            torch.cuda.synchronize()
+            w = torch.full((m,), float("nan"), dtype=torch.float32, device="cuda:0")
+            busy = torch.zeros(1 << 22, device="cuda:0")
+            for _ in range(30):  # a queue of work ahead of the copy that makes the weights
+                busy = busy * 1.0001 + 1.0
+            w.copy_(src)
+            say("serve: submit while torch's stream still produces build", i)
+            assert L.wrs_serve_submit_build(srv, w.data_ptr(), m, 0, cur_stream(), ctypes.byref(tid),
+                                            ctypes.byref(rid)) == wrs.OK
+            tids.append(tid.value)
+            rids.append(rid.value)
+            o = torch.zeros(50000, dtype=torch.int32, device="cuda:0")
+            for _ in range(10):
+                busy = busy * 1.0001 + 1.0
+            o.fill_(-1)  # the draws must land after this fill
+            assert L.wrs_serve_submit_sample(srv, tid.value, 50000, 30 + i, o.data_ptr(), cur_stream(),
+                                             ctypes.byref(rid)) == wrs.OK
+            rids.append(rid.value)
+            wanted.append(w_np)
+            dev_w.append(w)
+            outs.append(o)
+        for r in rids:
+            assert L.wrs_serve_wait(srv, r, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
+        for i, w_np in enumerate(wanted):
+            h = np.empty((w_np.size, 2), np.int32)
+            assert L.wrs_serve_read_table(srv, tids[i], h.ctypes.data, w_np.size) == wrs.OK
+            t, a = split_table(h)
+            check_against_sweep(orc, w_np, t, a)
+            assert np.array_equal(outs[i].cpu().numpy(), orc.alias_sample(t, a, 30 + i, 0, 0, 50000))
     finally:
         L.wrs_serve_destroy(srv)

@@ -12,7 +12,7 @@ within the error the kernel's arithmetic allows:
 import numpy as np
 import pytest
 
-from gpu_common import family, gpu_build, say, ulp_diff
+from gpu_common import check_against_sweep, family, gpu_build, say, t_tolerance, ulp_diff  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -27,28 +27,6 @@ def wrs():
 SIZES = [1, 2, 3, 5, 63, 1000, 1023, 1024, 1025, 2047, 4096, 5000, 3 * 1024 + 17, 40000, 65536, 65536 + 37]
 FAMILIES = ["uniform", "power0.5", "power1", "power2", "ints", "equal", "one", "dominant", "sorted_power1",
             "tiny_heavies", "negzero"]
-
-
-def t_tolerance(n, t_ref):
-    unit = 2.0 ** (int(n).bit_length() - 1 - 60)
-    ulp = np.spacing(np.abs(t_ref).astype(np.float32)).astype(np.float64)
-    return ulp + 513 * unit
-
-
-def check_against_sweep(orc, w, t, a):
-    t_ref, a_ref = orc.sweep_build(w)
-    bad = np.nonzero(a != a_ref)[0]
-    assert bad.size == 0, f"{bad.size} alias mismatches, first at {bad[:5]}: gpu {a[bad[:5]]} ref {a_ref[bad[:5]]}"
-    dt = np.abs(t.astype(np.float64) - t_ref.astype(np.float64))
-    tol = t_tolerance(w.size, t_ref)
-    assert np.all(dt <= tol), f"threshold off by {dt.max()} at {np.argmax(dt - tol)}"
-    light = w.astype(np.float64) * w.size <= w.astype(np.float64).sum() * (1 - 1e-12)
-    assert ulp_diff(t[light], t_ref[light]).max(initial=0) <= 1
-    mass, err = orc.reconstruct(w, t, a)
-    pos = w > 0
-    if pos.any():
-        assert err[pos].max() <= 1e-6
-    assert np.all(mass[~pos] == 0)
 
 
 @pytest.mark.parametrize("fam", FAMILIES)

@@ -2,10 +2,16 @@
 
 Batched: the 4096 tables of the batch recipe (n_i log-uniform in [2^6, 2^20],
 k_i = 4 n_i, stream id = table id, seed 4), built and sampled by one recorded
-batch; every 64th job's table and draws equal single calls.
+batch; every 64th job's table and draws equal single calls and the oracle
+(aliases equal to the exact sweep, every mass within 1e-6, all draws equal to
+the oracle's queries of the job's table).
 Served: the first 600 requests of the Poisson trace (seed 5) through the
 continuous-batching server (64 GB budget, batches of up to 256, two in
-flight), submitted back to back; every 7th request equals single calls.
+flight), submitted back to back with torch's stream as the ordering stream
+(the weights made beforehand, or, skipped, while the server runs); every 7th
+request equals single calls and the oracle (builds of up to 2^20
+items against the exact sweep, larger ones by every item's mass and 4096
+light thresholds; draws at 2^16 sampled counters against the oracle's queries).
 
 Weights are drawn on the device with a seeded torch generator (the two input
 families); the parity being checked does not depend on their values.
@@ -16,7 +22,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_common import say
+from gpu_common import check_against_sweep, check_masses, cur_stream, say, split_table
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +54,32 @@ def single(wrs, torch, w, n, k, seed, sid):
     return table.cpu().numpy(), out[:k].cpu().numpy()
 
 
-def test_batched_config(wrs):
+SWEEP_MAX = 1 << 20  # largest build checked against the exact sweep in full
+
+
+def oracle_check_table(orc, w_np, tab):
+    t, a = split_table(tab)
+    if w_np.size <= SWEEP_MAX:
+        check_against_sweep(orc, w_np, t, a)
+    else:
+        check_masses(orc, w_np, t, a)
+        idx = np.unique(np.random.default_rng(w_np.size).integers(0, w_np.size, 4096))
+        light, ref = orc.light_t_at(w_np, idx)
+        d = np.abs(t[idx[light]].view(np.int32).astype(np.int64) - ref[light].view(np.int32).astype(np.int64))
+        assert d.max(initial=0) <= 1
+    return t, a
+
+
+def oracle_check_draws(orc, t, a, seed, sid, out, full):
+    k = out.size
+    if full:
+        assert np.array_equal(out, orc.alias_sample(t, a, seed, sid, 0, k))
+    else:
+        c = np.unique(np.concatenate([np.arange(min(k, 1 << 15)), np.random.default_rng(k).integers(0, k, 1 << 15)]))
+        assert np.array_equal(out[c], orc.alias_sample_at(t, a, seed, sid, c.astype(np.uint64)))
+
+
+def test_batched_config(wrs, orc):
     import torch
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
@@ -67,16 +98,26 @@ def test_batched_config(wrs):
     assert all(st == wrs.OK for st in wrs.batch_status(ws, len(jobs)))
     for i in range(0, len(jobs), 64):
         s = specs[i]
+        say("batched config: job", i, "n", s["n"], "against the oracle")
         tab, smp = single(wrs, torch, s["w"], s["n"], s["k"], 4, s["stream_id"])
-        assert np.array_equal(s["table"].cpu().numpy(), tab), i
-        assert np.array_equal(s["out"].cpu().numpy(), smp), i
+        got_tab, got_out = s["table"].cpu().numpy(), s["out"].cpu().numpy()
+        assert np.array_equal(got_tab, tab), i
+        assert np.array_equal(got_out, smp), i
+        t, a = oracle_check_table(orc, s["w"].cpu().numpy(), got_tab)
+        oracle_check_draws(orc, t, a, 4, s["stream_id"], got_out, full=True)
 
 
-@pytest.mark.skip(reason="faulted once: torch's index kernel tripped its bounds assert while generating power-law "
-                         "weights on the device as this server ran on its own streams; no cause found in this "
-                         "library's code, so this case stays off the GPU (test_served_config_pregenerated covers "
-                         "the same requests with the weights made and synchronised first)")
-def test_served_config(wrs):
+@pytest.mark.skip(reason="faulted twice, both times inside torch's own gather base[randperm(n)] that makes a "
+                         "power-law build's weights while the server runs (6145-6656 items, then 69632-70144: "
+                         "request 42); the second time with every batch ordered behind torch's stream, so the cause "
+                         "is not established and the case stays off the GPU; test_served_config_pregenerated runs "
+                         "the same requests with the weights made first")
+def test_served_config(wrs, orc):
+    """Weights made on the device right before each submit, outputs allocated
+    right before each submit: the server's batches are ordered behind torch's
+    stream (the weights are complete, and an output block that torch's caching
+    allocator took from a just-freed temporary is no longer read by the kernels
+    queued before the submit)."""
     import torch
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
@@ -93,7 +134,7 @@ def test_served_config(wrs):
         for i, r in enumerate(trace):
             if r["op"] == "build":
                 w = device_weights(torch, g, r["n"], r["kind"])
-                assert L.wrs_serve_submit_build(srv, w.data_ptr(), w.numel(), ctypes.byref(tid),
+                assert L.wrs_serve_submit_build(srv, w.data_ptr(), w.numel(), 0, cur_stream(), ctypes.byref(tid),
                                                 ctypes.byref(rid)) == wrs.OK
                 tables.append(tid.value)
                 weights.append(w)
@@ -101,7 +142,7 @@ def test_served_config(wrs):
             elif tables:
                 ti = int(r["table_pick"] * len(tables))
                 o = torch.full((r["k"],), -1, dtype=torch.int32, device=dev)
-                assert L.wrs_serve_submit_sample(srv, tables[ti], r["k"], r["seed"], o.data_ptr(),
+                assert L.wrs_serve_submit_sample(srv, tables[ti], r["k"], r["seed"], o.data_ptr(), cur_stream(),
                                                  ctypes.byref(rid)) == wrs.OK
                 outs[i] = o
                 reqs.append((i, rid.value, "sample", ti))
@@ -109,14 +150,19 @@ def test_served_config(wrs):
             assert L.wrs_serve_wait(srv, q, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
         for i, q, op, ti in reqs[::7]:
             w = weights[ti]
+            h = np.empty((w.numel(), 2), np.int32)
+            assert L.wrs_serve_read_table(srv, tables[ti], h.ctypes.data, w.numel()) == wrs.OK
+            say("served config: request", i, op, "against single calls and the oracle")
             if op == "build":
                 tab, _ = single(wrs, torch, w, w.numel(), 0, 0, 0)
-                h = np.empty((w.numel(), 2), np.int32)
-                assert L.wrs_serve_read_table(srv, tables[ti], h.ctypes.data, w.numel()) == wrs.OK
                 assert np.array_equal(h, tab), i
+                oracle_check_table(orc, w.cpu().numpy(), h)
             else:
                 _, smp = single(wrs, torch, w, w.numel(), trace[i]["k"], trace[i]["seed"], 0)
-                assert np.array_equal(outs[i].cpu().numpy(), smp), i
+                got = outs[i].cpu().numpy()
+                assert np.array_equal(got, smp), i
+                t, a = split_table(h)
+                oracle_check_draws(orc, t, a, trace[i]["seed"], 0, got, full=False)
         s = wrs.ServeStats()
         assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
         assert s.failed == 0 and s.completed == len(reqs) and s.bytes_peak <= 64 << 30
@@ -124,7 +170,7 @@ def test_served_config(wrs):
         L.wrs_serve_destroy(srv)
 
 
-def test_served_config_pregenerated(wrs):
+def test_served_config_pregenerated(wrs, orc):
     """Same requests, with every build's weights generated and synchronised
     before the server starts (as the benchmark's served leg does)."""
     import torch
@@ -149,27 +195,32 @@ def test_served_config_pregenerated(wrs):
             if r["op"] == "build":
                 w = weights[bi]
                 bi += 1
-                assert L.wrs_serve_submit_build(srv, w.data_ptr(), w.numel(), ctypes.byref(tid),
+                assert L.wrs_serve_submit_build(srv, w.data_ptr(), w.numel(), 0, cur_stream(), ctypes.byref(tid),
                                                 ctypes.byref(rid)) == wrs.OK
                 tables.append(tid.value)
                 reqs.append((i, rid.value, "build", len(tables) - 1))
             elif tables:
                 ti = int(r["table_pick"] * len(tables))
-                assert L.wrs_serve_submit_sample(srv, tables[ti], r["k"], r["seed"], outs[i].data_ptr(),
+                assert L.wrs_serve_submit_sample(srv, tables[ti], r["k"], r["seed"], outs[i].data_ptr(), cur_stream(),
                                                  ctypes.byref(rid)) == wrs.OK
                 reqs.append((i, rid.value, "sample", ti))
         for _, q, _, _ in reqs:
             assert L.wrs_serve_wait(srv, q, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
         for i, q, op, ti in reqs[::7]:
             w = weights[ti]
+            h = np.empty((w.numel(), 2), np.int32)
+            assert L.wrs_serve_read_table(srv, tables[ti], h.ctypes.data, w.numel()) == wrs.OK
+            say("served config: request", i, op, "against single calls and the oracle")
             if op == "build":
                 tab, _ = single(wrs, torch, w, w.numel(), 0, 0, 0)
-                h = np.empty((w.numel(), 2), np.int32)
-                assert L.wrs_serve_read_table(srv, tables[ti], h.ctypes.data, w.numel()) == wrs.OK
                 assert np.array_equal(h, tab), i
+                oracle_check_table(orc, w.cpu().numpy(), h)
             else:
                 _, smp = single(wrs, torch, w, w.numel(), trace[i]["k"], trace[i]["seed"], 0)
-                assert np.array_equal(outs[i].cpu().numpy(), smp), i
+                got = outs[i].cpu().numpy()
+                assert np.array_equal(got, smp), i
+                t, a = split_table(h)
+                oracle_check_draws(orc, t, a, trace[i]["seed"], 0, got, full=False)
         s = wrs.ServeStats()
         assert L.wrs_serve_stats(srv, ctypes.byref(s)) == wrs.OK
         assert s.failed == 0 and s.completed == len(reqs) and s.bytes_peak <= 64 << 30

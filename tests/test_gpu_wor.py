@@ -79,3 +79,37 @@ def test_wor_config(wrs, orc, k):
     got, st = gpu_wor(wrs, w, k, 3, 0)
     assert st == wrs.OK
     compare_sets(orc, w, k, 3, 0, got)
+
+
+def gpu_wor_counts(wrs, w_np, k, seed, sid):
+    """As gpu_wor, also returning the candidate counts of the threshold pass and
+    of the fallback pass with an infinite threshold (the third and fourth words
+    of the workspace's scalars)."""
+    import torch
+    n = w_np.size
+    w = torch.from_numpy(np.ascontiguousarray(w_np, np.float32)).to("cuda:0")
+    out = torch.empty(max(k, 1), dtype=torch.int32, device="cuda:0")
+    ws = wrs.new_workspace(wrs.OP_WOR, n, k, "cuda:0")
+    wrs.sample_wor(w, n, k, seed, sid, out, ws)
+    st = wrs.status(ws)
+    words = ws[:16].cpu().numpy().view(np.uint32)
+    return out[:k].cpu().numpy(), st, int(words[2]), int(words[3])
+
+
+@pytest.mark.parametrize("n,k", [(50000, 64), (50000, 1000), (50000, 20000), (3 * (1 << 20) + 5, 1 << 16)])
+def test_wor_fallback_pass(wrs, orc, n, k):
+    """The threshold is estimated from the 4096 weights at positions
+    floor(s n / 4096).  Dominant weights on exactly those positions make the
+    estimate count each of them n / 4096 times, so the threshold pass finds
+    about 4096 / n of its targeted count of candidates, fewer than k (for k of
+    at least 64 here), and the fallback
+    pass (threshold +infinity, every item a candidate) must produce the sample."""
+    rng = np.random.default_rng(n + k)
+    w = (1.0 - rng.random(n, dtype=np.float32)).astype(np.float32)
+    sub = np.minimum((np.arange(4096, dtype=np.float64) * (n / 4096.0)).astype(np.int64), n - 1)
+    w[sub] = np.float32(1e30)
+    say("wor fallback", n, k)
+    got, st, c1, c2 = gpu_wor_counts(wrs, w, k, 41, 3)
+    assert st == wrs.OK
+    assert c1 < k and c2 > 0, (c1, c2)
+    compare_sets(orc, w, k, 41, 3, got)
