@@ -903,7 +903,7 @@ __device__ __forceinline__ void fetch_side(const JobDesc& J, int64_t c, int firs
     f.base = 0;
     if (cnt == 0) return;
     f.base = light ? glb(J.DP64)[c] : glb(J.EP64)[c];
-    const int k = (cnt + TPB - 1) / TPB;
+    const int k = uni((cnt + TPB - 1) / TPB);  // block-uniform: slots past it are skipped, not masked
     const int j0 = (int)threadIdx.x * k;
     const WRS_GLOBAL float* wp = glb(J.WP) + c * TILE + first;
     const WRS_GLOBAL uint16_t* po = glb(J.PO) + c * TILE + first;
@@ -929,7 +929,7 @@ template <bool LIGHT, bool LIST, class Id>
 __device__ __forceinline__ void fill_side(uint64_t* key, float* tl, Id* id, const SideFetch& f,
                                           const BuildScalars& sc, uint32_t n, double lscale,
                                           const u128* lres, uint64_t* tmp) {
-    const int k = (f.cnt + TPB - 1) / TPB;
+    const int k = uni((f.cnt + TPB - 1) / TPB);  // block-uniform: slots past it are skipped, not masked
     const int j0 = (int)threadIdx.x * k;
     const uint64_t Qk = sc.Qk;
     uint64_t inc[IPT];
@@ -938,7 +938,8 @@ __device__ __forceinline__ void fill_side(uint64_t* key, float* tl, Id* id, cons
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         inc[e] = 0;
-        if (e < k && j0 + e < f.cnt) {
+        if (e >= k) continue;
+        if (j0 + e < f.cnt) {
             uint64_t z;
             float t = 0.0f;
             if (LIST && is_residual_marker(__float_as_uint(f.v[e]))) {

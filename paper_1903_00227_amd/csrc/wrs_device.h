@@ -391,7 +391,28 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 // n q(w) / 2^kshift rounded to nearest (ties up): the item's size in key
 // units.  On the grid (s >= 0) n q = (n m) 2^s exactly; below it q is rounded
 // first.  The result is below 2^62 for every weight <= W.
+__device__ __forceinline__ uint64_t size_keyunits_any(float w, const BuildScalars& sc, uint32_t n);
+
+// size_keyunits for every lane of a wave: the common case (a zero weight, or
+// a weight on the grid whose size needs a right shift of 1 to 63 bits: every
+// weight within a factor of about 2^17 above and 2^40 below the mean) in a
+// few instructions; a wave with any other lane takes the general function.
 __device__ __forceinline__ uint64_t size_keyunits(float w, const BuildScalars& sc, uint32_t n) {
+    const uint32_t bits = __float_as_uint(w);
+    const uint32_t e = bits >> 23;
+    const uint32_t m = (bits & 0x7FFFFFu) | 0x800000u;
+    const int r = sc.kshift - ((int)e - 150 - sc.G);  // right shift of n m (e >= 1)
+    const bool zero = bits == 0u;
+    const bool common = zero || (e != 0u && r >= 1 && r <= 63);
+    if (__builtin_expect(__ballot(!common) == 0, 1)) {
+        const uint64_t x = (uint64_t)m * n;
+        const uint64_t z = (x + (1ull << ((r - 1) & 63))) >> (r & 63);
+        return zero ? 0ull : z;
+    }
+    return size_keyunits_any(w, sc, n);
+}
+
+__device__ __forceinline__ uint64_t size_keyunits_any(float w, const BuildScalars& sc, uint32_t n) {
     const uint32_t bits = __float_as_uint(w);
     const uint32_t e = bits >> 23;
     const uint32_t m = (bits & 0x7FFFFFu) | (e ? 0x800000u : 0u);
