@@ -206,6 +206,7 @@ def main():
         result["roofline"]["traffic_frac"] = round(tgbs / HBM_PEAK_GBS, 4)
     result["sampler_roofs"] = bench_roofs(torch, n, k, wrs.tune_get(wrs.TUNE_SAMPLE, k), samp_avg_ms)
     if not args.skip_extras:
+        result["small"] = bench_small(wrs, torch, workloads, not args.no_tune)
         result["build_plus"] = bench_plus(wrs, torch, inputs, n, table)
         result["two_level"] = bench_twolevel(wrs, torch, inputs, n, table, k, out)
         skewed = torch.from_numpy(workloads.power_law(n, 2.0, 2)).to(dev)
@@ -217,6 +218,43 @@ def main():
         result["served"] = bench_served(wrs, torch, np, workloads)
         result["cpu_baseline"] = bench_cpu(np, workloads)
     print(json.dumps(result), flush=True)
+
+
+def bench_small(wrs, torch, workloads, run_tune=True, reps=50):
+    """The small single-table workload (n = 2^16 uniform, seed 2; k = 2^20
+    draws, Philox key 2) in microseconds per call, and builds of other sizes:
+    each call bracketed by its own pair of events, median over `reps`."""
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream()
+    n1, k1 = 1 << 16, 1 << 20
+    sizes = (1 << 10, 1 << 16, 1 << 20, 1 << 24)
+    tuning = tune(wrs, list(sizes), [(n1, k1)], run_tune)
+
+    def median_us(fn):
+        fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record(st)
+            fn()
+            e1.record(st)
+        torch.cuda.synchronize()
+        return round(sorted(e0.elapsed_time(e1) for e0, e1 in ev)[reps // 2] * 1e3, 2)
+
+    res = {"workload": "n=2^16 uniform (seed 2), k=2^20 draws; builds of 2^10..2^24 items (uniform, seed 2)",
+           "tuning": tuning, "build_us": {}}
+    out = torch.empty(k1, dtype=torch.int32, device=dev)
+    for m in sizes:
+        w = torch.from_numpy(workloads.uniform(m, 2)).to(dev)
+        table = wrs.new_table(m, dev)
+        ws = wrs.new_workspace(wrs.OP_BUILD, m, 0, dev)
+        res["build_us"][f"2^{m.bit_length() - 1}"] = median_us(lambda: wrs.alias_build(w, m, table, ws))
+        assert wrs.status(ws) == wrs.OK
+        if m == n1:
+            res["n2p16_k2p20_sample_us"] = median_us(lambda: wrs.alias_sample(table, m, 2, 0, 0, k1, out))
+            res["n2p16_build_us"] = res["build_us"]["2^16"]
+        del w, table, ws
+    log(f"small: build 2^16 {res['n2p16_build_us']} us, 2^20 draws {res['n2p16_k2p20_sample_us']} us")
+    return res
 
 
 def bench_plus(wrs, torch, inputs, n, table, reps=5):
