@@ -90,6 +90,23 @@ size_t wrs_workspace_bytes(int op, int64_t n, int64_t k);
 int wrs_alias_build(const float* d_w, int64_t n, wrs_entry* d_table,
                     void* d_ws, size_t ws_bytes, void* stream);
 
+/* ---- building without allocation ------------------------------------------ */
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid allocation): wrs_alias_build with its
+ * workspace in a fixed device array of WRS_NOALLOC_SCRATCH_BYTES bytes that
+ * the library holds on every GPU it runs on, until the process ends, instead
+ * of caller memory.  Same table as wrs_alias_build.  n must satisfy
+ * wrs_workspace_bytes(WRS_OP_BUILD, n, 0) <= WRS_NOALLOC_SCRATCH_BYTES (about
+ * 2.2e7 items), else WRS_EINVAL and nothing is launched.  d_status (optional,
+ * device, 4-byte aligned): receives the build's status word (WRS_OK or
+ * WRS_EDOMAIN) on the stream.  The call allocates nothing and does not
+ * synchronise.  Every call on one GPU uses that GPU's array and leaves its
+ * contents there: calls that overlap on one GPU (streams not ordered against
+ * each other, or other threads) race. */
+#define WRS_NOALLOC_SCRATCH_BYTES (128u << 20)
+int wrs_alias_build_noalloc(const float* d_w, int64_t n, wrs_entry* d_table, int32_t* d_status, void* stream);
+
 /* Build an alias table with greedy blocks first (Section 4.2.1, PSA+).  The
  * items are cut into consecutive blocks of WRS_PSAPLUS_BLOCK items; inside
  * each block the sweep of Section 4.1 runs on the block's own items until the

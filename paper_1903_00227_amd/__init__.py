@@ -18,6 +18,7 @@ OK, EINVAL, EDOMAIN, ENOMEM, EDEVICE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, 
 OP_BUILD, OP_WOR, OP_BUILD_PLUS, OP_PERM, OP_TWOLEVEL, OP_OS = 1, 2, 3, 4, 5, 6
 TWOLEVEL_BLOCK = 2048  # items per block (meta-item) of the 2-level tables
 PSAPLUS_BLOCK = 2048  # items per greedy block of alias_build_plus
+NOALLOC_SCRATCH_BYTES = 128 << 20  # the fixed workspace of alias_build_noalloc
 SERVE_MAX_BATCH = 4096  # limits of ServeConfig.max_batch and ServeConfig.inflight
 SERVE_MAX_INFLIGHT = 16
 TUNE_BUILD, TUNE_SAMPLE = 1, 2
@@ -57,6 +58,8 @@ EXPORTS = {
     "wrs_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64]),
     "wrs_alias_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p]),
+    "wrs_alias_build_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
     "wrs_alias_build_plus": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_size_t, ctypes.c_void_p]),
     "wrs_permutation": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
@@ -185,6 +188,12 @@ def workspace_bytes(op: int, n: int, k: int = 0) -> int:
 
 def alias_build(w, n, table, ws, stream=None):
     _check("wrs_alias_build", lib().wrs_alias_build(_ptr(w), n, _ptr(table), _ptr(ws), ws.numel() if hasattr(ws, "numel") else ws_bytes_of(ws), _stream(stream)))
+
+
+def alias_build_noalloc(w, n, table, status_out=None, stream=None):
+    """Build with the library's fixed scratch array as workspace (allocates nothing)."""
+    _check("wrs_alias_build_noalloc", lib().wrs_alias_build_noalloc(_ptr(w), n, _ptr(table), _ptr(status_out),
+                                                                  _stream(stream)))
 
 
 def alias_build_plus(w, n, table, ws, stream=None):

@@ -22,6 +22,8 @@ void set_error(const char* fmt, ...) {
     va_end(ap);
 }
 
+void clear_error() { g_err[0] = 0; }
+
 static int dev_fail(const char* what, hipError_t e) {
     set_error("%s: %s", what, hipGetErrorString(e));
     return WRS_EDEVICE;

@@ -198,8 +198,9 @@ int launch_os_build(const float* d_w, int64_t n, void* d_os, void* d_ws, hipStre
 int launch_os_sample(const void* d_os, int64_t n, int64_t k, uint64_t seed, int32_t* d_items, int32_t* d_counts,
                      int64_t* d_s, void* d_ws, hipStream_t st);
 
-// Error reporting for the C ABI.
+// Error reporting for the C ABI (clear_error: empty this thread's text).
 void set_error(const char* fmt, ...);
+void clear_error();
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -144,3 +144,29 @@ def test_output_sensitive_host_validation(wrs):
     assert L.wrs_os_sample(fake, n, k, 1, fake, fake, s, fake, wbk - 1, None) == wrs.EINVAL
     assert L.wrs_os_sample(fake, n, k, 1, fake, fake, odd, fake, wbk, None) == wrs.EINVAL
     assert L.wrs_os_sample(fake, n, k, 1, fake, fake, s, odd, wbk, None) == wrs.EINVAL
+
+
+def test_noalloc_host_validation(wrs):
+    L = wrs.lib()
+    hdr = open(os.path.join(ROOT, "include", "wrs.h")).read()
+    m = re.search(r"#define WRS_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
+    assert m and wrs.NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every check below fails on the host
+    n = 1 << 20
+    assert L.wrs_alias_build_noalloc(None, n, fake, None, None) == wrs.EINVAL
+    assert L.wrs_alias_build_noalloc(fake, n, None, None, None) == wrs.EINVAL
+    assert L.wrs_alias_build_noalloc(fake, 0, fake, None, None) == wrs.EINVAL
+    assert L.wrs_alias_build_noalloc(fake, n, ctypes.c_void_p((1 << 20) + 4), None, None) == wrs.EINVAL
+    assert L.wrs_alias_build_noalloc(fake, n, fake, ctypes.c_void_p((1 << 20) + 2), None) == wrs.EINVAL
+    # the largest n whose workspace fits the scratch array, and the next one
+    lo, hi = 1, (1 << 31) - 1
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if L.wrs_workspace_bytes(wrs.OP_BUILD, mid, 0) <= wrs.NOALLOC_SCRATCH_BYTES:
+            lo = mid
+        else:
+            hi = mid - 1
+    assert lo > 1 << 24
+    assert L.wrs_alias_build_noalloc(fake, lo + 1, fake, None, None) == wrs.EINVAL
+    assert "scratch" in wrs.last_error()
+    assert L.wrs_alias_build_noalloc(fake, 1 << 30, fake, None, None) == wrs.EINVAL
