@@ -852,6 +852,26 @@ __global__ __launch_bounds__(TPB) void k_split(JobTable jt) {
     glb(J.pstart)[b] = pack_start(J, b);
 }
 
+// Number of entries of key[0, len) that are <= v (LE) or < v (!LE), for
+// ascending keys: a bisection whose trip count depends on len only (block-
+// uniform), with every probe inside [0, len).
+template <bool LE>
+__device__ __forceinline__ int count_below(const uint64_t* key, int len, uint64_t v) {
+    int base = 0;  // the count lies in [base, base + n]
+    int n = len;
+    while (n > 1) {
+        const int half = n >> 1;
+        const uint64_t k = key[base + half - 1];
+        base += (LE ? k <= v : k < v) ? half : 0;
+        n -= half;
+    }
+    if (len > 0) {
+        const uint64_t k = key[base];
+        base += (LE ? k <= v : k < v) ? 1 : 0;
+    }
+    return base;
+}
+
 // The two sides of the merge staged in LDS: the lights of tile x with the
 // deficit sum before each as key, and the heavies of tile y with the excess
 // sum through each.  Both come in index order from the partitioned copy of
@@ -1100,45 +1120,32 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                 store_entry(J.table, own, t, al);
             }
         } else if (m > 0) {
-            const int d0 = (int)(((int64_t)m * threadIdx.x) / TPB);
-            const int d1 = (int)(((int64_t)m * (threadIdx.x + 1)) / TPB);
-            if (d1 > d0) {
-                // merge path: largest j in [max(0,d0-nlc), min(d0,nhc)] with
-                // j == 0 or d0-j >= nlc or Bkey[j-1] <= Akey[d0-j]
-                int jlo = max(0, d0 - nlc), jhi = min(d0, nhc);
-                while (jlo < jhi) {
-                    const int mid = (jlo + jhi + 1) >> 1;
-                    const bool ok = (d0 - mid >= nlc) || (B.key[ph + mid - 1] <= A.key[pl + d0 - mid]);
-                    if (ok) jlo = mid; else jhi = mid - 1;
-                }
-                int j = jlo, i = d0 - jlo;
-                // keys at the two cursors: the next heavy of the cell, and the
-                // next light of the tile (Dend past the tile's last light)
-                uint64_t kb = (j < nhc) ? B.key[ph + j] : ~0ull;
-                uint64_t ka = (pl + i < nlx) ? A.key[pl + i] : Dend;
-                // One body for both kinds of bucket (the lanes of a wave
-                // disagree on the kind): a light aliases the next heavy not
-                // yet emitted (ph + j), a heavy the one after it.  Every LDS
-                // read is unconditional at a clamped index and both kinds'
-                // values are computed, so an iteration has no branch and its
-                // reads are issued together.
-                for (int d = d0; d < d1; ++d) {
-                    const bool take_h = (j < nhc) && (i >= nlc || kb <= ka);
-                    const int ia = min(pl + i, TILE - 1), ib = min(ph + j, TILE - 1);
-                    const int q = ph + j + (take_h ? 1 : 0);
-                    const uint32_t id_a = A.id[ia], id_b = B.id[ib], id_q = B.id[min(q, TILE - 1)];
-                    const float t_a = A.t[ia];
-                    const int64_t own = take_h ? item(bbase, id_b) : item(abase, id_a);
-                    const int32_t al = (q < nhy) ? (int32_t)item(bbase, id_q)
+            // Both kinds: every output takes its rank in the other side of the
+            // cell.  A light comes after the cell's heavies whose key is at
+            // most its own (ties put the heavy first), so it aliases the
+            // heavy at that rank; a heavy comes after the cell's lights whose
+            // key is below its own, so the next light is the one at that rank
+            // (Dend past the tile's last light).  Lanes take consecutive
+            // lights, then consecutive heavies.
+            const int nlc_u = uni(nlc), nhc_u = uni(nhc);
+            for (int d = threadIdx.x; d < m; d += TPB) {
+                if (d < nlc_u) {
+                    const int lp = pl + d;
+                    const int r = count_below<true>(B.key + ph, nhc_u, A.key[lp]);
+                    const int q = ph + r;
+                    const int64_t own = item(abase, A.id[lp]);
+                    const int32_t al = (q < nhy) ? (int32_t)item(bbase, B.id[min(q, TILE - 1)])
                                                  : (nextH != FH_NONE ? nextH : (int32_t)own);
-                    const float t_h = heavy_t(kb, ka, tscale);
-                    store_entry(J.table, own, take_h ? t_h : t_a, al);
-                    j += take_h ? 1 : 0;
-                    i += take_h ? 0 : 1;
-                    // the keys at both cursors; only the one that moved is taken
-                    const uint64_t nkb = B.key[min(ph + j, TILE - 1)], nka = A.key[min(pl + i, TILE - 1)];
-                    kb = take_h ? ((j < nhc) ? nkb : ~0ull) : kb;
-                    ka = take_h ? ka : ((pl + i < nlx) ? nka : Dend);
+                    store_entry(J.table, own, A.t[lp], al);
+                } else {
+                    const int hp = ph + (d - nlc_u);
+                    const uint64_t E = B.key[hp];
+                    const int r = count_below<false>(A.key + pl, nlc_u, E);
+                    const uint64_t Dn = (pl + r < nlx) ? A.key[min(pl + r, TILE - 1)] : Dend;
+                    const int64_t own = item(bbase, B.id[hp]);
+                    const int32_t al = (hp + 1 < nhy) ? (int32_t)item(bbase, B.id[min(hp + 1, TILE - 1)])
+                                                      : (nextH != FH_NONE ? nextH : (int32_t)own);
+                    store_entry(J.table, own, heavy_t(E, Dn, tscale), al);
                 }
             }
         }
