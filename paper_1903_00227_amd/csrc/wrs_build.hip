@@ -510,28 +510,65 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
         uint32_t nl = 0;
         u128 sq = 0, sql = 0;
         int fh = FH_NONE;
-        int smin = 0;
-        // (a zero weight, and a marker's 0, is 0 on the branch-free path too)
+        // Narrow lanes: when every nonzero weight of a lane lies on the grid,
+        // within 2^36 of the lane's smallest one, each of its 16 q values is
+        // below 2^60 at the scale of that smallest one, so the lane's two sums
+        // are exact in one 64-bit word each and are scaled up once.
+        bool narrow = false;
+        if constexpr (!LIST) {
+            int slo = 0x7FFFFFFF, shi = -1;
 #pragma unroll
-        for (int k = 0; k < 4 * AGG_VEC; ++k) smin = min(smin, qw(k) != 0.0f ? grid_shift(qw(k), G) : 0);
-        if (__ballot(smin < 0) == 0) {
-            // every weight of the tile lies on the grid
+            for (int k = 0; k < 4 * AGG_VEC; ++k) {
+                const uint32_t bits = __float_as_uint(v[k]);
+                const int sk = grid_shift(v[k], G);
+                slo = bits != 0u ? min(slo, sk) : slo;
+                shi = bits != 0u ? max(shi, sk) : shi;
+            }
+            const bool ok = shi < 0 ? slo == 0x7FFFFFFF : (slo >= 0 && shi - slo <= 36);
+            narrow = __ballot(!ok) == 0;
+            if (narrow) {
+                const int s0 = shi < 0 ? 0 : slo;  // a lane of zeros sums to 0 at any scale
+                uint64_t a = 0, al = 0;
 #pragma unroll
-            for (int r = 0; r < AGG_VEC; ++r) {
+                for (int r = 0; r < AGG_VEC; ++r) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const bool light = is_light(r, e);
-                    const u128 q = quantize_on_grid(qw(4 * r + e), G);
+                    for (int e = 0; e < 4; ++e) {
+                        const uint32_t bits = __float_as_uint(v[4 * r + e]);
+                        const uint32_t ex = bits >> 23;
+                        const uint64_t m = (bits & 0x7FFFFFu) | (ex ? 0x800000u : 0u);
+                        const uint64_t x = m << ((grid_shift(v[4 * r + e], G) - s0) & 63);
+                        a += x;
+                        al += is_light(r, e) ? x : 0ull;
+                    }
+                }
+                sq = (u128)a << s0;
+                sql = (u128)al << s0;
+            }
+        }
+        if (!narrow) {
+            int smin = 0;
+            // (a zero weight, and a marker's 0, is 0 on the branch-free path too)
+#pragma unroll
+            for (int k = 0; k < 4 * AGG_VEC; ++k) smin = min(smin, qw(k) != 0.0f ? grid_shift(qw(k), G) : 0);
+            if (__ballot(smin < 0) == 0) {
+                // every weight of the tile lies on the grid
+#pragma unroll
+                for (int r = 0; r < AGG_VEC; ++r) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const bool light = is_light(r, e);
+                        const u128 q = quantize_on_grid(qw(4 * r + e), G);
+                        sq += q;
+                        sql += light ? q : (u128)0;
+                    }
+                }
+            } else {
+                for (int k = 0; k < 4 * AGG_VEC; ++k) {
+                    const bool light = is_light(k >> 2, k & 3);
+                    const u128 q = quantize(qw(k), G);
                     sq += q;
                     sql += light ? q : (u128)0;
                 }
-            }
-        } else {
-            for (int k = 0; k < 4 * AGG_VEC; ++k) {
-                const bool light = is_light(k >> 2, k & 3);
-                const u128 q = quantize(qw(k), G);
-                sq += q;
-                sql += light ? q : (u128)0;
             }
         }
 #pragma unroll
