@@ -1105,6 +1105,22 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
     const HeavySlot<LIST>& B = sh.B;
     // original item of a staged entry: tile base + offset, or the list's index
     auto item = [&](int64_t tbase, uint32_t id) -> int64_t { return LIST ? (int64_t)id : tbase + id; };
+    // A table index is a tile's base plus an offset that k_tileagg wrote for
+    // an item of that tile, so it lies in [0, n) whatever the weights held
+    // when each kernel read them.  The guard turns a violation into
+    // WRS_EDEVICE instead of a stray write.  (List mode writes the original
+    // indices of a list that the host's earlier stage built.)
+    // (Selects, not a branch: a violation is recorded and the write goes to
+    // entry n - 1 of a table whose build then fails.)
+    bool bad = false;
+    auto put = [&](int64_t own, float t, int32_t al) {
+        if constexpr (!LIST) {
+            const bool out = (uint64_t)own >= (uint64_t)J.n;
+            bad |= out;
+            own = out ? J.n - 1 : own;
+        }
+        store_entry(J.table, own, t, al);
+    };
     for (int64_t s = s0; s < s1; ++s) {
         const int xi = (int)(x - x0), yi = (int)(y - y0);
         const bool has_h = y + 1 <= C;
@@ -1143,7 +1159,7 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                 const int64_t own = item(abase, A.id[lp]);
                 const float t = A.t[lp];
                 const int32_t a2 = (!hv && al == FH_NONE) ? (int32_t)own : al;
-                store_entry(J.table, own, t, a2);
+                put(own, t, a2);
             }
         } else if (nlc == 0 && nhc > 0) {
             // heavies only: each keeps 1 + (E - D) with the same next light
@@ -1154,7 +1170,7 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                 const int64_t own = item(bbase, B.id[hp]);
                 const int32_t al = (hp + 1 < nhy) ? (int32_t)item(bbase, B.id[hp + 1])
                                                   : (nextH != FH_NONE ? nextH : (int32_t)own);
-                store_entry(J.table, own, t, al);
+                put(own, t, al);
             }
         } else if (m > 0) {
             // Both kinds: every output takes its rank in the other side of the
@@ -1173,7 +1189,7 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                     const int64_t own = item(abase, A.id[lp]);
                     const int32_t al = (q < nhy) ? (int32_t)item(bbase, B.id[min(q, TILE - 1)])
                                                  : (nextH != FH_NONE ? nextH : (int32_t)own);
-                    store_entry(J.table, own, A.t[lp], al);
+                    put(own, A.t[lp], al);
                 } else {
                     const int hp = ph + (d - nlc_u);
                     const uint64_t E = B.key[hp];
@@ -1182,7 +1198,7 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
                     const int64_t own = item(bbase, B.id[hp]);
                     const int32_t al = (hp + 1 < nhy) ? (int32_t)item(bbase, B.id[min(hp + 1, TILE - 1)])
                                                       : (nextH != FH_NONE ? nextH : (int32_t)own);
-                    store_entry(J.table, own, heavy_t(E, Dn, tscale), al);
+                    put(own, heavy_t(E, Dn, tscale), al);
                 }
             }
         }
@@ -1204,6 +1220,7 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
             }
         }
     }
+    if (!LIST && __ballot(bad) != 0 && (threadIdx.x & 63) == 0) glb(J.sc)->status = WRS_EDEVICE;
 }
 
 // ---------------------------------------------------------------------------
