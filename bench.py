@@ -481,6 +481,20 @@ def bench_batched(wrs, torch, np, workloads, run_tune=True):
     e1.record()
     torch.cuda.synchronize()
     fused_ms = e0.elapsed_time(e1) / reps
+    # the same batch with its small tables (n <= 8192) in the one-workgroup-per-table launch
+    wrs.batch_fuse_small(wrs.FUSE_MAX_N)
+    try:
+        wrs.batch_build_sample(arr, ws)      # records that batch's graph
+        torch.cuda.synchronize()
+        assert all(s == wrs.OK for s in wrs.batch_status(ws, len(jobs)))
+        e0.record()
+        for _ in range(reps):
+            wrs.batch_build_sample(arr, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        small_ms = e0.elapsed_time(e1) / reps
+    finally:
+        wrs.batch_fuse_small(0)
     # one call per table, same kernels
     sws = [wrs.new_workspace(wrs.OP_BUILD, s["n"], 0, dev) for s in specs]
     torch.cuda.synchronize()
@@ -495,6 +509,8 @@ def bench_batched(wrs, torch, np, workloads, run_tune=True):
     return {"workload": "4096 tables, n_i log-uniform in [2^6,2^20], k_i = 4 n_i (seed 4)",
             "items": items, "draws": draws, "fused_ms": round(fused_ms, 3), "tuning": tuning,
             "one_at_a_time_ms": round(single_ms, 3), "speedup": round(single_ms / fused_ms, 2),
+            "small_tables_in_one_workgroup_ms": round(small_ms, 3),
+            "small_tables": sum(1 for j in jobs if j["n"] <= wrs.FUSE_MAX_N),
             "fused_gitems_s": round(items / (fused_ms * 1e-3) / 1e9, 3),
             "fused_hbm_frac_28B_per_item": round(28.0 * items / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 

@@ -275,6 +275,17 @@ int wrs_batch_status(const void* d_ws, int32_t njobs, void* stream, int* h_statu
  * 0: plain stream launches every call. */
 int wrs_batch_graph_mode(int enable);
 
+/* Small tables in one persistent launch: with max_n > 0, every job of a batch
+ * with n <= max_n is built and sampled by one workgroup, in one launch for all
+ * such jobs beside the phase launches of the others; the workgroup runs the
+ * construction's phases one after another and draws the samples from the
+ * finished table copied into LDS (WRS_FUSE_MAX_N items at most).  Tables and
+ * samples are the same bits as without it.  0 (default) gives every job to the
+ * phase launches, which measure faster on the batches this library is timed
+ * on.  WRS_EINVAL for max_n outside [0, WRS_FUSE_MAX_N].  Per process. */
+#define WRS_FUSE_MAX_N 8192
+int wrs_batch_fuse_small(int32_t max_n);
+
 /* ---- launch-parameter tuning -------------------------------------------- */
 
 /* Two launch parameters are free and never change a result: the tile events

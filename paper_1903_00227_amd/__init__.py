@@ -19,6 +19,7 @@ OP_BUILD, OP_WOR, OP_BUILD_PLUS, OP_PERM, OP_TWOLEVEL, OP_OS = 1, 2, 3, 4, 5, 6
 TWOLEVEL_BLOCK = 2048  # items per block (meta-item) of the 2-level tables
 PSAPLUS_BLOCK = 2048  # items per greedy block of alias_build_plus
 NOALLOC_SCRATCH_BYTES = 128 << 20  # the fixed workspace of alias_build_noalloc
+FUSE_MAX_N = 8192  # largest batched table the fused small-table launch takes
 SERVE_MAX_BATCH = 4096  # limits of ServeConfig.max_batch and ServeConfig.inflight
 SERVE_MAX_INFLIGHT = 16
 TUNE_BUILD, TUNE_SAMPLE = 1, 2
@@ -90,6 +91,7 @@ EXPORTS = {
     "wrs_batch_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_int)]),
     "wrs_batch_graph_mode": (ctypes.c_int, [ctypes.c_int]),
+    "wrs_batch_fuse_small": (ctypes.c_int, [ctypes.c_int32]),
     "wrs_tune_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
     "wrs_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int32]),
     "wrs_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
@@ -296,6 +298,11 @@ def batch_status(ws, njobs, stream=None):
 
 def batch_graph_mode(enable: bool):
     lib().wrs_batch_graph_mode(1 if enable else 0)
+
+
+def batch_fuse_small(max_n: int):
+    """Batched jobs with n <= max_n (0: none) go to the fused small-table launch."""
+    _check("wrs_batch_fuse_small", lib().wrs_batch_fuse_small(max_n))
 
 
 # ---- launch-parameter tuning (result-neutral) ----

@@ -297,14 +297,16 @@ extern "C" int wrs_total_weight(const void* d_ws, void* stream, double* hi, doub
 
 // ---------------------------------------------------------------------------
 // Batches.  Workspace: [JobDesc x njobs][offsets PH_COUNT x (njobs+1)]
-// [BuildScalars x njobs][per-job build workspaces].
+// [indices of the small jobs x njobs][BuildScalars x njobs][per-job build
+// workspaces].  A small job (n <= FUSE_MAX) gets no block in the phase
+// launches: the fused launch builds and samples it.
 // ---------------------------------------------------------------------------
 namespace wrs {
 
 static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BatchHeader {
-    size_t jobs_off, off_off, sc_off, data_off, total;
+    size_t jobs_off, off_off, small_off, sc_off, data_off, total;
 };
 
 static BatchHeader batch_header(int32_t njobs) {
@@ -312,6 +314,7 @@ static BatchHeader batch_header(int32_t njobs) {
     size_t o = 0;
     h.jobs_off = o; o = a256(o + sizeof(JobDesc) * njobs);
     h.off_off = o;  o = a256(o + sizeof(int64_t) * PH_COUNT * (njobs + 1));
+    h.small_off = o; o = a256(o + sizeof(int32_t) * njobs);
     h.sc_off = o;   o = a256(o + sizeof(BuildScalars) * njobs);
     h.data_off = o;
     h.total = o;
@@ -330,6 +333,7 @@ static std::mutex g_batch_mu;
 static std::unordered_map<std::string, BatchPlan*> g_plans;
 static uint64_t g_plan_clock = 0;
 static bool g_graph_mode = true;
+static int32_t g_fuse_max = 0;  // batched jobs with n <= this go to the fused launch
 
 static void destroy_plan(BatchPlan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -356,12 +360,25 @@ extern "C" int wrs_batch_graph_mode(int enable) {
     return WRS_OK;
 }
 
+extern "C" int wrs_batch_fuse_small(int32_t max_n) {
+    static_assert(WRS_FUSE_MAX_N == FUSE_MAX, "the header's limit is the kernel's LDS table size");
+    g_err[0] = 0;
+    if (max_n < 0 || max_n > FUSE_MAX) {
+        set_error("wrs_batch_fuse_small: max_n = %d out of [0, %d]", (int)max_n, FUSE_MAX);
+        return WRS_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    g_fuse_max = max_n;
+    return WRS_OK;
+}
+
 static int batch_record(const wrs_job* h_jobs, int32_t njobs, void* d_ws, hipStream_t st, JobTable& jt,
-                        int64_t* totals, std::vector<char>& host_blob) {
+                        int64_t* totals, std::vector<char>& host_blob, const int32_t** d_small, int32_t* nsmall) {
     BatchHeader h = batch_header(njobs);
     char* base = (char*)d_ws;
     std::vector<JobDesc> descs(njobs);
     std::vector<int64_t> off((size_t)PH_COUNT * (njobs + 1), 0);
+    std::vector<int32_t> small;
     size_t o = h.data_off;
     for (int32_t j = 0; j < njobs; ++j) {
         JobDesc& J = descs[j];
@@ -378,12 +395,19 @@ static int batch_record(const wrs_job* h_jobs, int32_t njobs, void* d_ws, hipStr
         J.sc = (BuildScalars*)(base + h.sc_off) + j;  // statuses side by side
         int64_t b[PH_COUNT];
         phase_blocks(J, b);
+        if (h_jobs[j].n <= g_fuse_max) {
+            small.push_back(j);
+            for (int p = 0; p < PH_COUNT; ++p) b[p] = 0;
+        }
         for (int p = 0; p < PH_COUNT; ++p) off[(size_t)p * (njobs + 1) + j + 1] = off[(size_t)p * (njobs + 1) + j] + b[p];
     }
     for (int p = 0; p < PH_COUNT; ++p) totals[p] = off[(size_t)p * (njobs + 1) + njobs];
     host_blob.assign(h.data_off, 0);
     memcpy(host_blob.data() + h.jobs_off, descs.data(), sizeof(JobDesc) * njobs);
     memcpy(host_blob.data() + h.off_off, off.data(), sizeof(int64_t) * off.size());
+    if (!small.empty()) memcpy(host_blob.data() + h.small_off, small.data(), sizeof(int32_t) * small.size());
+    *d_small = (const int32_t*)(base + h.small_off);
+    *nsmall = (int32_t)small.size();
     memset(&jt, 0, sizeof jt);
     jt.jobs = (const JobDesc*)(base + h.jobs_off);
     jt.off = (const int64_t*)(base + h.off_off);
@@ -411,13 +435,15 @@ extern "C" int wrs_batch_build_sample(const wrs_job* h_jobs, int32_t njobs, void
     JobTable jt;
     int64_t totals[PH_COUNT];
     std::vector<char> blob;
-    batch_record(h_jobs, njobs, d_ws, st, jt, totals, blob);
-
+    const int32_t* d_small = nullptr;
+    int32_t nsmall = 0;
     std::lock_guard<std::mutex> g(g_batch_mu);
+    batch_record(h_jobs, njobs, d_ws, st, jt, totals, blob, &d_small, &nsmall);
     std::string key((const char*)h_jobs, sizeof(wrs_job) * njobs);
     key.append((const char*)&d_ws, sizeof d_ws);
     const uint64_t gen = tuning_generation();
     key.append((const char*)&gen, sizeof gen);
+    key.append((const char*)&g_fuse_max, sizeof g_fuse_max);
     if (g_graph_mode) {
         auto it = g_plans.find(key);
         if (it != g_plans.end()) {
@@ -438,10 +464,32 @@ extern "C" int wrs_batch_build_sample(const wrs_job* h_jobs, int32_t njobs, void
     if (e != hipSuccess) return dev_fail("upload batch descriptors", e);
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return dev_fail("upload batch descriptors", e);
+    // The small jobs' launch runs beside the phase launches of the others, on
+    // a library stream forked from the caller's and joined back (in a recorded
+    // graph: a parallel branch).  It holds one workgroup per CU and waits on
+    // its own barriers most of the time; alone on the stream it would add its
+    // whole duration.
+    static hipStream_t side = nullptr;
+    static hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    if (nsmall > 0 && !side) {
+        e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) return dev_fail("create the small-job stream", e);
+    }
     auto launch_all = [&]() -> hipError_t {
-        hipError_t r = launch_build(jt, totals, st);
-        if (r != hipSuccess) return r;
-        return launch_sample(jt, totals[PH_SAMPLE], st);
+        hipError_t r = hipSuccess;
+        if (nsmall > 0) {
+            r = hipEventRecord(ev_fork, st);
+            if (r == hipSuccess) r = hipStreamWaitEvent(side, ev_fork, 0);
+            if (r == hipSuccess) r = launch_fused_small(jt, d_small, nsmall, side);
+            if (r == hipSuccess) r = hipEventRecord(ev_join, side);
+            if (r != hipSuccess) return r;
+        }
+        r = launch_build(jt, totals, st);
+        if (r == hipSuccess) r = launch_sample(jt, totals[PH_SAMPLE], st);
+        if (r == hipSuccess && nsmall > 0) r = hipStreamWaitEvent(st, ev_join, 0);
+        return r;
     };
     if (!g_graph_mode) {
         e = launch_all();

@@ -239,12 +239,15 @@ __device__ __forceinline__ void block_reduce_dd(double& hi, double& lo, uint32_t
 
 __device__ void finalize_scalars(const JobDesc& J, double hi, double lo, uint32_t bad, uint32_t pos);
 
-__global__ __launch_bounds__(TPB) void k_reduce(JobTable jt) {
-    __shared__ int s_job;
-    __shared__ double s_hi[TPB / 64], s_lo[TPB / 64];
-    __shared__ uint32_t s_bad[TPB / 64], s_pos[TPB / 64];
-    int64_t lb;
-    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
+// The block bodies of the construction's phases take (job, block of the
+// job, LDS): the phase kernels run one body per block, and the fused kernel
+// for small batched tables runs every phase's bodies in one workgroup.
+struct RedShared {
+    double hi[TPB / 64], lo[TPB / 64];
+    uint32_t bad[TPB / 64], pos[TPB / 64];
+};
+
+__device__ __forceinline__ void reduce_block(const JobDesc& J, int64_t lb, RedShared& sh) {
     const int64_t base = lb * RED_CHUNK;
     const int64_t end = min(base + (int64_t)RED_CHUNK, J.n);
     const WRS_GLOBAL float* w = glb(J.w);
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(TPB) void k_reduce(JobTable jt) {
     } else {
         for (int64_t i = base + threadIdx.x; i < end; i += TPB) red_item(w[i], hi, lo, bad, pos);
     }
-    block_reduce_dd(hi, lo, bad, pos, s_hi, s_lo, s_bad, s_pos);
+    block_reduce_dd(hi, lo, bad, pos, sh.hi, sh.lo, sh.bad, sh.pos);
     if (threadIdx.x == 0) {
         J.red[lb] = make_double2(hi, lo);
         J.redinfo[2 * lb] = bad;
@@ -273,6 +276,14 @@ __global__ __launch_bounds__(TPB) void k_reduce(JobTable jt) {
         // no block for this job; the scalars are the same bits either way)
         if (J.nred == 1) finalize_scalars(J, hi, lo, bad, pos);
     }
+}
+
+__global__ __launch_bounds__(TPB) void k_reduce(JobTable jt) {
+    __shared__ int s_job;
+    __shared__ RedShared sh;
+    int64_t lb;
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
+    reduce_block(J, lb, sh);
 }
 
 __device__ __forceinline__ u128 u128_from_integral_double(double d) {
@@ -414,12 +425,13 @@ constexpr int AGG_VEC = TILE / 256;  // float4 loads per lane
 // FH holds original indices, and the partitioned copy carries original
 // indices (PI) instead of tile offsets.
 template <bool LIST>
-__global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
-    __shared__ int s_job;
-    __shared__ float s_w[TILES_PER_AGG_BLOCK][TILE];
-    __shared__ uint32_t s_o[TILES_PER_AGG_BLOCK][LIST ? TILE : TILE / 2];  // u16 offsets, or u32 indices
-    int64_t lb;
-    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
+struct TileaggShared {
+    float w[TILES_PER_AGG_BLOCK][TILE];
+    uint32_t o[TILES_PER_AGG_BLOCK][LIST ? TILE : TILE / 2];  // u16 offsets, or u32 indices
+};
+
+template <bool LIST>
+__device__ __forceinline__ void tileagg_block(const JobDesc& J, int64_t lb, TileaggShared<LIST>& sh) {
     const BuildScalars* sc = J.sc;
     if (sc->status != WRS_OK) return;  // the same for the whole block
     const int wv = threadIdx.x >> 6;
@@ -432,7 +444,7 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
     const int64_t n = J.n;
     const uint32_t nmul = J.nmul;
     const int64_t base = c * TILE;
-    uint16_t* s_o16 = (uint16_t*)&s_o[wv][0];
+    uint16_t* s_o16 = (uint16_t*)&sh.o[wv][0];
     if (active) {
         const int cnt = (int)min((int64_t)TILE, n - base);
         const WRS_GLOBAL float* w = glb(J.w) + base;
@@ -595,8 +607,8 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
                 const bool light = (lm[e] >> lane) & 1ull;
                 const int p = light ? (int)lr : (int)(nl + (uint32_t)i - lr);
                 if (i < cnt) {
-                    s_w[wv][p] = v[4 * r + e];
-                    if constexpr (LIST) s_o[wv][p] = oid[4 * r + e]; else s_o16[p] = (uint16_t)i;
+                    sh.w[wv][p] = v[4 * r + e];
+                    if constexpr (LIST) sh.o[wv][p] = oid[4 * r + e]; else s_o16[p] = (uint16_t)i;
                 }
                 lr += light;
             }
@@ -623,11 +635,11 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
         for (int r = 0; r < AGG_VEC; ++r) {
             const int i0 = r * 256 + lane * 4;
             vfloat4 x;
-            x.x = s_w[wv][i0]; x.y = s_w[wv][i0 + 1]; x.z = s_w[wv][i0 + 2]; x.w = s_w[wv][i0 + 3];
+            x.x = sh.w[wv][i0]; x.y = sh.w[wv][i0 + 1]; x.z = sh.w[wv][i0 + 2]; x.w = sh.w[wv][i0 + 3];
             *(WRS_GLOBAL vfloat4*)(wp + i0) = x;
             if constexpr (LIST) {
                 vuint4 o;
-                o.x = s_o[wv][i0]; o.y = s_o[wv][i0 + 1]; o.z = s_o[wv][i0 + 2]; o.w = s_o[wv][i0 + 3];
+                o.x = sh.o[wv][i0]; o.y = sh.o[wv][i0 + 1]; o.z = sh.o[wv][i0 + 2]; o.w = sh.o[wv][i0 + 3];
                 *(WRS_GLOBAL vuint4*)(glb(J.PI) + base + i0) = o;
             } else {
                 vuint2 o;
@@ -637,6 +649,15 @@ __global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
             }
         }
     }
+}
+
+template <bool LIST>
+__global__ __launch_bounds__(TPB) void k_tileagg(JobTable jt) {
+    __shared__ int s_job;
+    __shared__ TileaggShared<LIST> sh;
+    int64_t lb;
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
+    tileagg_block<LIST>(J, lb, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -682,12 +703,12 @@ __device__ __forceinline__ int32_t pack_start(const JobDesc& J, int64_t b) {
     return (int32_t)lo;
 }
 
-__global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
-    __shared__ int s_job;
-    __shared__ ScanTmp tmp;
-    __shared__ int s_w[TPB / 64];
-    int64_t lb;
-    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
+struct ScanSegShared {
+    ScanTmp tmp;
+    int w[TPB / 64];
+};
+
+__device__ __forceinline__ void scan_seg_block(const JobDesc& J, int64_t lb, ScanSegShared& sh) {
     if (J.sc->status != WRS_OK) return;
     const int64_t C = J.ntiles;
     const int64_t t0 = lb * SCAN_SEG + (int64_t)threadIdx.x * SEG_PER_THREAD;
@@ -718,8 +739,8 @@ __global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
     }
     uint32_t nl_ex, nl_tot;
     u128 dp_ex, ep_ex, dp_tot, ep_tot;
-    block_scan3(snl, sdp, sep, nl_ex, dp_ex, ep_ex, nl_tot, dp_tot, ep_tot, tmp);
-    const int later = block_suffix_min_excl(fmin, s_w);
+    block_scan3(snl, sdp, sep, nl_ex, dp_ex, ep_ex, nl_tot, dp_tot, ep_tot, sh.tmp);
+    const int later = block_suffix_min_excl(fmin, sh.w);
     int suf = later;
 #pragma unroll
     for (int e = SEG_PER_THREAD - 1; e >= 0; --e) {
@@ -766,6 +787,14 @@ __global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
         __syncthreads();
         for (int64_t b = threadIdx.x; b < J.npack; b += TPB) glb(J.pstart)[b] = pack_start(J, b);
     }
+}
+
+__global__ __launch_bounds__(TPB) void k_scan_seg(JobTable jt) {
+    __shared__ int s_job;
+    __shared__ ScanSegShared sh;
+    int64_t lb;
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &s_job));
+    scan_seg_block(J, lb, sh);
 }
 
 __global__ __launch_bounds__(TPB) void k_scan_top(JobTable jt) {
@@ -1046,10 +1075,7 @@ __device__ __forceinline__ void fill_side(uint64_t* key, float* tl, Id* id, cons
 
 
 template <bool LIST>
-__global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
-    __shared__ PackShared<LIST> sh;
-    int64_t lb;
-    const JobDesc J = job_uniform(job_of_block(jt, lb, &sh.s_job, xcd_contiguous_block()));
+__device__ __forceinline__ void pack_block(const JobDesc& J, int64_t lb, PackShared<LIST>& sh) {
     if (J.sc->status != WRS_OK) return;
     const BuildScalars sc = scalars_uniform(J.sc);
     const uint32_t n32 = J.nmul;
@@ -1223,9 +1249,28 @@ __global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
     if (!LIST && __ballot(bad) != 0 && (threadIdx.x & 63) == 0) glb(J.sc)->status = WRS_EDEVICE;
 }
 
+template <bool LIST>
+__global__ __launch_bounds__(TPB) void k_pack(JobTable jt) {
+    __shared__ PackShared<LIST> sh;
+    int64_t lb;
+    const JobDesc J = job_uniform(job_of_block(jt, lb, &sh.s_job, xcd_contiguous_block()));
+    pack_block<LIST>(J, lb, sh);
+}
+
 // ---------------------------------------------------------------------------
 // a6: alias queries (Section 2.2 query; select without a branch as in Section 10).
 // ---------------------------------------------------------------------------
+// Bucket r in [0, n) and coin u in [0, 1) of the draw with counter c: one
+// Philox block; r = floor((x1 2^32 + x0) n / 2^64) for n < 2^31, u from 24 bits.
+__device__ __forceinline__ void draw_of(uint64_t c, uint32_t sid, uint32_t k0, uint32_t k1, uint64_t n, uint32_t& r,
+                                        float& u) {
+    const uint4 x = philox4x32_10(make_uint4((uint32_t)c, (uint32_t)(c >> 32), sid, 0u), k0, k1);
+    const uint64_t lo = ((uint64_t)x.x * n) >> 32;
+    const uint64_t hi = (uint64_t)x.y * n + lo;
+    r = (uint32_t)(hi >> 32);
+    u = (float)(x.z >> 8) * (1.0f / 16777216.0f);
+}
+
 __global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
     __shared__ int s_job;
     int64_t lb;
@@ -1245,13 +1290,7 @@ __global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
     for (int e = 0; e < SAMPLE_UNROLL_MAX; ++e) {
         if (e < U) {
             const int64_t s = s0 + (int64_t)e * SAMPLE_TPB;
-            const uint64_t c = J.first_counter + (uint64_t)s;
-            const uint4 x = philox4x32_10(make_uint4((uint32_t)c, (uint32_t)(c >> 32), J.stream_id, 0u), k0, k1);
-            // floor((x1 2^32 + x0) n / 2^64) for n < 2^31
-            const uint64_t lo = ((uint64_t)x.x * n) >> 32;
-            const uint64_t hi = (uint64_t)x.y * n + lo;
-            r[e] = (uint32_t)(hi >> 32);
-            u[e] = (float)(x.z >> 8) * (1.0f / 16777216.0f);
+            draw_of(J.first_counter + (uint64_t)s, J.stream_id, k0, k1, n, r[e], u[e]);
         }
     }
     uint64_t ent[SAMPLE_UNROLL_MAX];
@@ -1271,6 +1310,65 @@ __global__ __launch_bounds__(SAMPLE_TPB) void k_sample(JobTable jt) {
             glb(J.out)[s] = (u[e] < t) ? (int32_t)r[e] : a;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Small batched tables (n <= FUSE_MAX): one persistent launch in which a
+// workgroup takes a job at a time through every phase above (the same block
+// bodies, one after another, with a barrier between phases), then copies the
+// finished table into LDS and draws the job's samples from there.  A job's
+// table and draws are the ones its single calls give, bit for bit: each phase
+// computes the same values whichever workgroup runs its blocks, and draw s is
+// a function of its counter alone.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_fused_small(JobTable jt, const int32_t* small, int32_t nsmall) {
+    __shared__ union FusedShared {
+        RedShared r;
+        TileaggShared<false> t;
+        ScanSegShared s;
+        PackShared<false> p;
+    } u;
+    __shared__ uint64_t s_tab[FUSE_MAX];
+    for (int32_t q = (int32_t)blockIdx.x; q < nsmall; q += (int32_t)gridDim.x) {
+        const JobDesc J = job_uniform(jt.jobs[glb(small)[q]]);
+        // one block of each phase whose job size allows one (n <= FUSE_MAX:
+        // one reduction block, one scan segment), every block of the others
+        reduce_block(J, 0, u.r);
+        __syncthreads();
+        for (int64_t lb = 0; lb < cdiv(J.ntiles, TILES_PER_AGG_BLOCK); ++lb) {
+            tileagg_block<false>(J, lb, u.t);
+            __syncthreads();
+        }
+        scan_seg_block(J, 0, u.s);
+        __syncthreads();
+        for (int64_t lb = 0; lb < J.npack; ++lb) {
+            pack_block<false>(J, lb, u.p);
+            __syncthreads();
+        }
+        const bool ok = uni((uint32_t)glb(J.sc)->status) == (uint32_t)WRS_OK;
+        if (ok && J.k > 0) {
+            const WRS_GLOBAL uint64_t* table = (const WRS_GLOBAL uint64_t*)glb(J.table);
+            for (int64_t i = threadIdx.x; i < J.n; i += TPB) s_tab[i] = table[i];
+            __syncthreads();
+            const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
+            for (int64_t s = threadIdx.x; s < J.k; s += TPB) {
+                uint32_t r;
+                float uu;
+                draw_of(J.first_counter + (uint64_t)s, J.stream_id, k0, k1, (uint64_t)J.n, r, uu);
+                const uint64_t ent = s_tab[r];
+                const float t = __uint_as_float((uint32_t)ent);
+                const int32_t a = (int32_t)(uint32_t)(ent >> 32);
+                glb(J.out)[s] = (uu < t) ? (int32_t)r : a;
+            }
+        }
+        __syncthreads();  // before the next job reuses the LDS
+    }
+}
+
+hipError_t launch_fused_small(const JobTable& jt, const int32_t* d_small, int32_t nsmall, hipStream_t st) {
+    if (nsmall <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fused_small, dim3((unsigned)min(nsmall, FUSE_BLOCKS)), dim3(TPB), 0, st, jt, d_small, nsmall);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

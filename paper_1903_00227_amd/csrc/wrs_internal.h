@@ -21,6 +21,8 @@ constexpr int PACK_STEPS_MAX = 32;
 constexpr int RED_CHUNK = 65536;    // items per block of the total-weight reduction
 constexpr int SCAN_SEG = 2048;      // tiles per segment of the tile scan
 constexpr int SAMPLE_TPB = 256;     // threads per block of the sampler
+constexpr int FUSE_MAX = 8192;      // batched tables up to this size: one workgroup per job, table in LDS
+constexpr int FUSE_BLOCKS = 512;    // workgroups of that launch at most
 constexpr int SAMPLE_UNROLL_MAX = 8;  // draws per thread of the sampler: tuned per size class (1..8)
 
 // Per-table scalars written by the reduction, read by every later phase.
@@ -172,6 +174,8 @@ hipError_t launch_twolvl(const JobDesc& J, const TwoLayout& T, hipStream_t st);
 hipError_t launch_sample2(const wrs_entry* top, const wrs_entry* table, int64_t n, uint64_t seed, uint32_t sid,
                           uint64_t first, int64_t k, int32_t* out, hipStream_t st);
 hipError_t launch_sample(const JobTable& jt, int64_t blocks, hipStream_t st);
+// Jobs d_small[0, nsmall) of jt (each n <= FUSE_MAX), built and sampled in one launch.
+hipError_t launch_fused_small(const JobTable& jt, const int32_t* d_small, int32_t nsmall, hipStream_t st);
 // jt.jobs[j].sc->status -> d_dst[j] for every job (device memory, jobs on the device)
 hipError_t launch_collect_status(const JobTable& jt, int32_t* d_dst, hipStream_t st);
 

@@ -170,3 +170,15 @@ def test_noalloc_host_validation(wrs):
     assert L.wrs_alias_build_noalloc(fake, lo + 1, fake, None, None) == wrs.EINVAL
     assert "scratch" in wrs.last_error()
     assert L.wrs_alias_build_noalloc(fake, 1 << 30, fake, None, None) == wrs.EINVAL
+
+
+def test_batch_fuse_small_host_validation(wrs):
+    L = wrs.lib()
+    hdr = open(os.path.join(ROOT, "include", "wrs.h")).read()
+    m = re.search(r"#define WRS_FUSE_MAX_N (\d+)", hdr)
+    assert m and wrs.FUSE_MAX_N == int(m.group(1))
+    assert L.wrs_batch_fuse_small(-1) == wrs.EINVAL
+    assert L.wrs_batch_fuse_small(wrs.FUSE_MAX_N + 1) == wrs.EINVAL
+    assert "max_n" in wrs.last_error()
+    assert L.wrs_batch_fuse_small(wrs.FUSE_MAX_N) == wrs.OK
+    assert L.wrs_batch_fuse_small(0) == wrs.OK

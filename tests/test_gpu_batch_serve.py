@@ -41,28 +41,36 @@ def make_batch(wrs, jobs):
     return specs
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_batch_equals_single_calls(wrs, graph):
+@pytest.mark.parametrize("graph,fuse", [(True, 0), (False, 0), (True, 8192), (False, 8192), (True, 1000)])
+def test_batch_equals_single_calls(wrs, graph, fuse):
+    """fuse > 0: jobs with n <= fuse go to the fused small-table launch (every
+    such job is checked on the first call)."""
     import torch
     jobs = workloads.batch_jobs(seed=4, count=300, lo_log2=0, hi_log2=17)
     specs = make_batch(wrs, jobs)
     arr = wrs.make_jobs(specs)
     ws = torch.empty(wrs.batch_workspace_bytes(arr), dtype=torch.uint8, device="cuda:0")
     wrs.batch_graph_mode(graph)
-    say("batch", len(jobs), "graph" if graph else "stream")
-    for rep in range(4):  # later calls replay the recorded graph, with eager work in between
-        for s in specs:
-            s["table"].fill_(-1)
-            s["out"].fill_(-1)
-        wrs.batch_build_sample(arr, ws)
-        torch.cuda.synchronize()
-        assert all(st == wrs.OK for st in wrs.batch_status(ws, len(jobs)))
-        for i in range(0, len(jobs), 7):
-            s = specs[i]
-            tab, smp = single(wrs, s["w"], s["n"], s["k"], 4, s["stream_id"])
-            assert np.array_equal(s["table"].cpu().numpy(), tab), (rep, i)
-            assert np.array_equal(s["out"][:s["k"]].cpu().numpy(), smp), (rep, i)
-    wrs.batch_graph_mode(True)
+    wrs.batch_fuse_small(fuse)
+    say("batch", len(jobs), "graph" if graph else "stream", "fused up to", fuse)
+    try:
+        for rep in range(4):  # later calls replay the recorded graph, with eager work in between
+            for s in specs:
+                s["table"].fill_(-1)
+                s["out"].fill_(-1)
+            wrs.batch_build_sample(arr, ws)
+            torch.cuda.synchronize()
+            assert all(st == wrs.OK for st in wrs.batch_status(ws, len(jobs)))
+            for i in range(len(jobs)):
+                s = specs[i]
+                if i % 7 and not (rep == 0 and s["n"] <= fuse):
+                    continue
+                tab, smp = single(wrs, s["w"], s["n"], s["k"], 4, s["stream_id"])
+                assert np.array_equal(s["table"].cpu().numpy(), tab), (rep, i)
+                assert np.array_equal(s["out"][:s["k"]].cpu().numpy(), smp), (rep, i)
+    finally:
+        wrs.batch_graph_mode(True)
+        wrs.batch_fuse_small(0)
 
 
 def test_batch_graphs_share_a_workspace(wrs):
@@ -91,17 +99,31 @@ def test_batch_graphs_share_a_workspace(wrs):
             assert np.array_equal(s["out"][:s["k"]].cpu().numpy(), smp), (step, i)
 
 
-def test_batch_reports_bad_job(wrs):
+@pytest.mark.parametrize("fuse", [0, 8192])
+def test_batch_reports_bad_job(wrs, fuse):
     import torch
     jobs = workloads.batch_jobs(seed=6, count=5, lo_log2=3, hi_log2=10)
     specs = make_batch(wrs, jobs)
     specs[2]["w"][1] = float("nan")
+    for s in specs:
+        s["out"].fill_(-1)
     arr = wrs.make_jobs(specs)
     ws = torch.empty(wrs.batch_workspace_bytes(arr), dtype=torch.uint8, device="cuda:0")
-    say("batch with a bad job")
-    wrs.batch_build_sample(arr, ws)
-    st = wrs.batch_status(ws, len(jobs))
+    say("batch with a bad job, fused up to", fuse)
+    wrs.batch_fuse_small(fuse)
+    try:
+        wrs.batch_build_sample(arr, ws)
+        st = wrs.batch_status(ws, len(jobs))
+    finally:
+        wrs.batch_fuse_small(0)
     assert st[2] == wrs.EDOMAIN and all(st[i] == wrs.OK for i in (0, 1, 3, 4))
+    # the failed job draws nothing; the others equal their single calls
+    assert (specs[2]["out"][:specs[2]["k"]].cpu().numpy() == -1).all()
+    for i in (0, 1, 3, 4):
+        s = specs[i]
+        tab, smp = single(wrs, s["w"], s["n"], s["k"], 4, s["stream_id"])
+        assert np.array_equal(s["table"].cpu().numpy(), tab), i
+        assert np.array_equal(s["out"][:s["k"]].cpu().numpy(), smp), i
 
 
 def run_server(wrs, reqs, weights, one_at_a_time, budget=8 << 30):
