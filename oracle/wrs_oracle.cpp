@@ -756,18 +756,22 @@ extern "C" int orc_reconstruct(const float* w, const float* t, const int32_t* a,
 /* ------------------------------------------------------------------------- */
 /* Exponential clocks (Section 2.3): key_i = -ln(u_i) / w_i with u_i uniform  */
 /* in (0,1]; the k smallest keys are a weighted sample without replacement.   */
-/* Bits: Philox key = seed, counter = (i lo, i hi, stream id, 1),              */
-/* u_i = (x0 + 1) 2^-32.  Zero weights get key +inf.  Ties in the key are      */
-/* broken by the smaller item index.  FP64 throughout.                          */
+/* Bits: one Philox block serves four consecutive items: key = seed, counter  */
+/* = (g lo, g hi, stream id, 1) for g = floor(i / 4), and u_i = (x_j + 1) 2^-32 */
+/* with j = i mod 4.  Zero weights get key +inf.  Ties in the key are broken   */
+/* by the smaller item index.  FP64 throughout.                                 */
+static double wor_uniform(uint64_t seed, uint32_t stream_id, int64_t i) {
+    uint32_t x[4];
+    philox_at(seed, (uint64_t)i >> 2, stream_id, 1u, x);
+    return ((double)x[i & 3] + 1.0) * (1.0 / 4294967296.0);
+}
+
 /* ------------------------------------------------------------------------- */
 extern "C" int orc_wor_keys(const float* w, int64_t n, uint64_t seed, uint32_t stream_id, double* keys) {
     if (!w || !keys || n < 1 || n > 2147483647LL) return ORC_EINVAL;
     if (!valid_weights(w, n)) return ORC_EDOMAIN;
     for (int64_t i = 0; i < n; ++i) {
-        uint32_t x[4];
-        philox_at(seed, (uint64_t)i, stream_id, 1u, x);
-        double u = ((double)x[0] + 1.0) * (1.0 / 4294967296.0);
-        double e = -log(u);
+        double e = -log(wor_uniform(seed, stream_id, i));
         keys[i] = w[i] > 0.0f ? e / (double)w[i] : INFINITY;
     }
     return ORC_OK;
@@ -802,10 +806,7 @@ extern "C" int orc_wor_keys_at(const float* w, int64_t n, uint64_t seed, uint32_
     for (int64_t s = 0; s < m; ++s) {
         int64_t i = idx[s];
         if (i < 0 || i >= n) return ORC_EINVAL;
-        uint32_t x[4];
-        philox_at(seed, (uint64_t)i, stream_id, 1u, x);
-        double u = ((double)x[0] + 1.0) * (1.0 / 4294967296.0);
-        keys[s] = w[i] > 0.0f ? -log(u) / (double)w[i] : INFINITY;
+        keys[s] = w[i] > 0.0f ? -log(wor_uniform(seed, stream_id, i)) / (double)w[i] : INFINITY;
     }
     return ORC_OK;
 }
