@@ -220,8 +220,9 @@ int wrs_alias_sample(const wrs_entry* d_table, int64_t n, uint64_t seed, uint32_
                      uint64_t first_counter, int64_t k, int32_t* d_out, void* stream);
 
 /* Sample k distinct items without replacement (problem WRS-N, Section 1) by
- * exponential clocks (Section 2.3): u_i = (x0 + 1) 2^-32 from Philox with
- * counter (i low, i high, stream_id, 1), key_i = -ln(u_i) / w_i (FP64), and the
+ * exponential clocks (Section 2.3): u_i = (x_j + 1) 2^-32 from word j = i mod 4
+ * of the Philox block with counter (g low, g high, stream_id, 1), g = floor(i / 4),
+ * key_i = -ln(u_i) / w_i (FP64), and the
  * k smallest keys, ties broken by the smaller index, win.  d_out receives the
  * k indices in ascending order.  Requires 0 <= k and, on the device, k <= the
  * number of positive weights (else status WRS_EDOMAIN).  d_ws:

@@ -95,21 +95,40 @@ __global__ void k_perm_init(PermScalars* sc) {
 }
 
 // Key of every item: bits of -ln(u_i)/w_i (+inf for a zero weight), value i.
-__global__ __launch_bounds__(256) void k_perm_keys(const float* w, int64_t n, uint64_t seed, uint32_t sid,
-                                                   uint64_t* keys, uint32_t* vals, PermScalars* sc) {
+// A thread takes four consecutive items, the four words of one Philox block
+// (item 4g + j takes word j of block g).
+constexpr int PK_TPB = 256;
+__global__ __launch_bounds__(PK_TPB) void k_perm_keys(const float* w, int64_t n, uint64_t seed, uint32_t sid,
+                                                      uint64_t* keys, uint32_t* vals, PermScalars* sc) {
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) {
-        const float raw = glb(w)[i];
-        const bool bad = !(raw >= 0.0f) || isinf(raw);  // on the weight as given (-0 passes)
-        const float v = canonical_weight(raw);
-        const uint4 x = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)((uint64_t)i >> 32), sid, 1u),
+    const int64_t g = (int64_t)blockIdx.x * PK_TPB + threadIdx.x;
+    const int64_t i0 = 4 * g;
+    if (i0 < n) {
+        float raw[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if ((((uintptr_t)w) & 15) == 0 && i0 + 3 < n) {
+            const vfloat4 x = *(const WRS_GLOBAL vfloat4*)(glb(w) + i0);
+            raw[0] = x.x; raw[1] = x.y; raw[2] = x.z; raw[3] = x.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (i0 + j < n) raw[j] = glb(w)[i0 + j];
+        }
+        const uint4 x = philox4x32_10(make_uint4((uint32_t)g, (uint32_t)((uint64_t)g >> 32), sid, 1u),
                                       (uint32_t)seed, (uint32_t)(seed >> 32));
-        const double key = (v > 0.0f) ? neg_log_u(x.x) / (double)v : INFINITY;
-        glb(keys)[i] = (uint64_t)__double_as_longlong(key);
-        glb(vals)[i] = (uint32_t)i;
+        const uint32_t xw[4] = {x.x, x.y, x.z, x.w};
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < n) {
+                bad |= !(raw[j] >= 0.0f) || isinf(raw[j]);  // on the weight as given (-0 passes)
+                const float v = canonical_weight(raw[j]);
+                const double key = (v > 0.0f) ? neg_log_u(xw[j]) / (double)v : INFINITY;
+                glb(keys)[i0 + j] = (uint64_t)__double_as_longlong(key);
+                glb(vals)[i0 + j] = (uint32_t)(i0 + j);
+            }
+        }
         if (bad) s_bad = 1;
     }
     __syncthreads();
@@ -383,7 +402,7 @@ int launch_perm(const float* d_w, int64_t n, uint64_t seed, uint32_t sid, int32_
     } while (0)
     hipLaunchKernelGGL(k_perm_init, dim3(1), dim3(64), 0, st, P.sc);
     WRS_CHECK();
-    hipLaunchKernelGGL(k_perm_keys, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, d_w, n, seed, sid, P.kA, P.vA,
+    hipLaunchKernelGGL(k_perm_keys, dim3((unsigned)cdiv(n, 4 * PK_TPB)), dim3(PK_TPB), 0, st, d_w, n, seed, sid, P.kA, P.vA,
                        P.sc);
     WRS_CHECK();
     uint64_t* kin = P.kA;

@@ -1,12 +1,13 @@
 // wrs_wor.hip -- sampling without replacement by exponential clocks (Section 2.3).
 //
-// key_i = -ln(u_i) / w_i with u_i = (x0 + 1) 2^-32 from Philox counter
-// (i, stream_id, 1); the k smallest keys (ties: smaller index) are the sample.
+// key_i = -ln(u_i) / w_i with u_i = (x_j + 1) 2^-32 from word j = i mod 4 of
+// the Philox block with counter (floor(i / 4), stream_id, 1); the k smallest
+// keys (ties: smaller index) are the sample.
 // Keys are generated once, in one pass over the weights:
 //   k_wor_tau     threshold tau with E[#{key <= tau}] ~ 1.02 k + 4 sqrt(k) + 64,
 //                 from a strided subsample of the weights (Newton on the
 //                 expected count sum_i 1 - exp(-w_i tau), which is concave)
-//   k_wor_filter  Philox per item; since -ln(u) >= 1 - u, an item with
+//   k_wor_filter  one Philox block per four items; since -ln(u) >= 1 - u, an item with
 //                 1 - u > tau w cannot have key <= tau and skips the logarithm;
 //                 survivors are staged in LDS, get the exact FP64 key together
 //                 (one per lane, no divergence) and are appended if <= tau.
@@ -127,10 +128,10 @@ __device__ __forceinline__ unsigned long long* shard_word(const WorArgs& A, int 
     return A.shard + ((size_t)((pass - 1) * 2 + what) * WOR_SHARDS + s) * WOR_SHARD_STRIDE;
 }
 
-__device__ __forceinline__ uint32_t wor_x0(const WorArgs& A, int64_t i) {
-    const uint4 x = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)((uint64_t)i >> 32), A.sid, 1u),
-                                  (uint32_t)A.seed, (uint32_t)(A.seed >> 32));
-    return x.x;
+// The Philox block of items 4g .. 4g+3: item 4g + j takes word j.
+__device__ __forceinline__ uint4 wor_block(const WorArgs& A, int64_t g) {
+    return philox4x32_10(make_uint4((uint32_t)g, (uint32_t)((uint64_t)g >> 32), A.sid, 1u), (uint32_t)A.seed,
+                         (uint32_t)(A.seed >> 32));
 }
 
 
@@ -245,31 +246,45 @@ __global__ __launch_bounds__(WOR_TPB) void k_wor_filter(WorArgs A, int pass) {
     const int64_t base = (int64_t)blockIdx.x * (WOR_TPB * WOR_IPT);
     // Phase 1, per item: domain check, Philox, and the prefilter 1 - u <= tau w
     // (a key -ln(u) / w <= tau implies it since -ln(u) >= 1 - u).  Survivors are
-    // staged; the logarithm waits for phase 2, where every lane has one.
+    // staged; the logarithm waits for phase 2, where every lane has one.  A
+    // thread takes four consecutive items at a time, the four words of one
+    // Philox block.
+    const bool vec = (((uintptr_t)A.w) & 15) == 0;
     uint32_t nst = 0;  // staged by this wave (the same in all its lanes)
-#pragma unroll 2
-    for (int e = 0; e < WOR_IPT; ++e) {
-        const int64_t i = base + (int64_t)e * WOR_TPB + threadIdx.x;
-        bool pre = false;
-        uint32_t x0 = 0;
-        float v = 0.0f;
-        if (i < n) {
-            v = A.w[i];
-            bad |= (uint32_t)(!(v >= 0.0f) || isinf(v));
-            if (v > 0.0f && !isinf(v)) {
-                x0 = wor_x0(A, i);
-                const double omu = (double)(0xFFFFFFFFu - x0) * (1.0 / 4294967296.0);  // 1 - u
-                pre = omu <= tau * (double)v * (1.0 + 1e-12);
+    for (int e = 0; e < WOR_IPT / 4; ++e) {
+        const int64_t i0 = base + 4 * ((int64_t)e * WOR_TPB + threadIdx.x);
+        float v4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (vec && i0 + 3 < n) {
+            const vfloat4 x = *(const WRS_GLOBAL vfloat4*)(glb(A.w) + i0);
+            v4[0] = x.x; v4[1] = x.y; v4[2] = x.z; v4[3] = x.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (i0 + j < n) v4[j] = glb(A.w)[i0 + j];
+        }
+        const uint4 xb = wor_block(A, i0 >> 2);
+        const uint32_t xw[4] = {xb.x, xb.y, xb.z, xb.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = i0 + j;
+            const float v = v4[j];
+            bool pre = false;
+            if (i < n) {
+                bad |= (uint32_t)(!(v >= 0.0f) || isinf(v));
+                if (v > 0.0f && !isinf(v)) {
+                    const double omu = (double)(0xFFFFFFFFu - xw[j]) * (1.0 / 4294967296.0);  // 1 - u
+                    pre = omu <= tau * (double)v * (1.0 + 1e-12);
+                }
             }
+            const unsigned long long mask = __ballot(pre);
+            if (pre) {
+                const uint32_t p = wbase + nst + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                s_key[p] = ((uint64_t)xw[j] << 32) | __float_as_uint(v);
+                s_idx[p] = (int32_t)i;
+            }
+            nst += (uint32_t)__popcll(mask);
         }
-        const unsigned long long mask = __ballot(pre);
-        if (pre) {
-            const uint32_t p = wbase + nst + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-            s_key[p] = ((uint64_t)x0 << 32) | __float_as_uint(v);
-            s_idx[p] = (int32_t)i;
-        }
-        nst += (uint32_t)__popcll(mask);
     }
     // Phase 2 (per wave): keys of the staged items, 64 at a time, and an
     // ordered compaction of the candidates (key <= tau) in place.  A lane's
