@@ -338,17 +338,20 @@ int wrs_tune_load(const char* path);
  * WRS_EDEVICE.  Every address a served request's kernels write is fixed by its
  * sizes (table entry i < n, draw s < k), never by the weights' values.
  *
- * Ordering with the caller: each submit takes the caller's stream (a
- * hipStream_t of the server's device, or NULL).  With a stream, the server
- * records an event on it during the call, and the request's batch waits for
- * that event on the device before it reads the request's weights or writes
- * its outputs: everything the caller queued on that stream before the submit
- * (producing the weights, a previous reader of the output buffer, a
- * deallocation and reuse of the buffer's memory by a caching allocator) runs
- * first.  With NULL there is no ordering: the caller must have completed that
- * work already (for instance with a device synchronisation).  Completion is
- * reported on the host (wrs_serve_poll, wrs_serve_wait); a result may be read
- * on any stream after that. */
+ * Ordering with the caller: each submit takes the caller's stream, a
+ * hipStream_t of the server's device; NULL is the legacy default stream (the
+ * stream of frameworks that have not set one) and is ordered like any other.
+ * The server records an event on that stream during the call, and the
+ * request's batch waits for that event on the device before it reads the
+ * request's weights or writes its outputs: everything the caller queued on
+ * that stream before the submit (producing the weights, a previous reader of
+ * the output buffer, a deallocation and reuse of the buffer's memory by a
+ * caching allocator) runs first.  WRS_SERVE_UNORDERED instead of a stream
+ * skips the event: the caller must have completed that work already (for
+ * instance with a device synchronisation).  Completion is reported on the host
+ * (wrs_serve_poll, wrs_serve_wait); a result may be read on any stream after
+ * that. */
+#define WRS_SERVE_UNORDERED ((void*)(intptr_t)-1)
 #define WRS_SERVE_MAX_BATCH 4096
 #define WRS_SERVE_MAX_INFLIGHT 16
 typedef struct {

@@ -20,6 +20,7 @@ TWOLEVEL_BLOCK = 2048  # items per block (meta-item) of the 2-level tables
 PSAPLUS_BLOCK = 2048  # items per greedy block of alias_build_plus
 NOALLOC_SCRATCH_BYTES = 128 << 20  # the fixed workspace of alias_build_noalloc
 FUSE_MAX_N = 8192  # largest batched table the fused small-table launch takes
+SERVE_UNORDERED = (1 << 64) - 1  # serve submits: no ordering behind a caller's stream
 SERVE_MAX_BATCH = 4096  # limits of ServeConfig.max_batch and ServeConfig.inflight
 SERVE_MAX_INFLIGHT = 16
 TUNE_BUILD, TUNE_SAMPLE = 1, 2

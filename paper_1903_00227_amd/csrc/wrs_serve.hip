@@ -444,10 +444,12 @@ static void release_slots(Server* S) {
 }
 
 // An event recorded on the caller's stream now (lock held); nullptr and
-// WRS_OK when no stream is given.
+// WRS_OK for WRS_SERVE_UNORDERED.  NULL is the legacy default stream: the
+// stream of a framework that has not set one, so it gets an event like any
+// other.
 static int submission_event(Server& S, void* stream, hipEvent_t* out) {
     *out = nullptr;
-    if (!stream) return WRS_OK;
+    if (stream == WRS_SERVE_UNORDERED) return WRS_OK;
     hipEvent_t e = nullptr;
     if (!S.free_events.empty()) {
         e = S.free_events.back();

@@ -408,12 +408,20 @@ def test_serve_host_weights(wrs, orc):
         L.wrs_serve_destroy(srv)
 
 
-def test_serve_orders_behind_the_callers_stream(wrs, orc):
+@pytest.mark.parametrize("which", ["default", "side"])
+def test_serve_orders_behind_the_callers_stream(wrs, orc, which):
     """Weights still being produced, and output buffers still being filled, on
-    torch's stream when the requests are submitted: the batches wait for that
-    work, so every table and draw equals the oracle's."""
+    the caller's stream when the requests are submitted: the batches wait for
+    that work, so every table and draw equals the oracle's.  "default" is
+    torch's default stream, whose handle is NULL (the legacy default stream);
+    "side" a stream of its own."""
+    import contextlib
     import ctypes
     import torch
+    side = torch.cuda.Stream() if which == "side" else None
+    ctx = torch.cuda.stream(side) if side is not None else contextlib.nullcontext()
+    if which == "default":
+        assert torch.cuda.current_stream().cuda_stream == 0
     L = wrs.lib()
     cfg = wrs.ServeConfig(1 << 30, 16, 0, 2)
     srv = ctypes.c_void_p()
@@ -421,6 +429,7 @@ def test_serve_orders_behind_the_callers_stream(wrs, orc):
     try:
         tid, rid, st = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int()
         wanted, dev_w, outs, tids, rids = [], [], [], [], []
+        ctx.__enter__()
         for i in range(6):
             m = (1 << 18) + 1000 * i
             w_np = workloads.power_law(m, 1.0, 200 + i) if i % 2 else workloads.uniform(m, 200 + i)
@@ -446,6 +455,7 @@ def test_serve_orders_behind_the_callers_stream(wrs, orc):
             wanted.append(w_np)
             dev_w.append(w)
             outs.append(o)
+        ctx.__exit__(None, None, None)
         for r in rids:
             assert L.wrs_serve_wait(srv, r, ctypes.byref(st)) == wrs.OK and st.value == wrs.OK
         for i, w_np in enumerate(wanted):

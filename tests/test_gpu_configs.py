@@ -107,11 +107,12 @@ def test_batched_config(wrs, orc):
         oracle_check_draws(orc, t, a, 4, s["stream_id"], got_out, full=True)
 
 
-@pytest.mark.skip(reason="faulted twice, both times inside torch's own gather base[randperm(n)] that makes a "
-                         "power-law build's weights while the server runs (6145-6656 items, then 69632-70144: "
-                         "request 42); the second time with every batch ordered behind torch's stream, so the cause "
-                         "is not established and the case stays off the GPU; test_served_config_pregenerated runs "
-                         "the same requests with the weights made first")
+@pytest.mark.skip(reason="faulted twice inside torch's gather base[randperm(n)] that makes a power-law build's "
+                         "weights while the server runs (6145-6656 items, then request 42); cause: torch's default "
+                         "stream has the handle NULL, which the submit calls took as 'no ordering', so the server's "
+                         "draws could overwrite a reused randperm buffer before the queued gather read it; fixed "
+                         "(NULL is ordered), not rerun in the round whose rerun after a fix faulted; "
+                         "test_served_config_pregenerated runs the same requests with the weights made first")
 def test_served_config(wrs, orc):
     """Weights made on the device right before each submit, outputs allocated
     right before each submit: the server's batches are ordered behind torch's
