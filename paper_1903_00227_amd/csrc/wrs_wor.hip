@@ -18,7 +18,7 @@
 //                 takes more than a few hundred atomics; k_wor_shards turns
 //                 the 64 counts into a prefix table, and later kernels address
 //                 candidate c through it.
-//   k_wor_hist / k_wor_find   select of the k-th smallest key over the
+//   k_wor_hist / k_wor_find / k_wor_radix   select of the k-th smallest key over the
 //                 candidates, by levels of 16384 bins until at most 8192
 //                 candidates share the target bin: two levels of linear bins on
 //                 the key (enough when the candidates are the threshold pass's),
@@ -26,6 +26,7 @@
 //                 time from the top (a non-negative double's bit pattern orders
 //                 like its value), which resolve any spread of keys, such as
 //                 the fallback pass's, unless more than 8192 keys are equal
+//                 (the radix levels run in one workgroup, k_wor_radix)
 //   k_wor_gather / k_wor_final  sort that bin in LDS, take the exact k-th (key, idx)
 //   k_wor_mark    set one bit per selected item in an n-bit map
 //   k_wor_popc / k_wor_popscan / k_wor_compact   emit the set bits in index order
@@ -455,8 +456,10 @@ __global__ __launch_bounds__(WOR_CAND_TPB) void k_wor_hist(WorArgs A, int level)
         if (h[i]) atomicAdd(&g[i], h[i]);
 }
 
-__global__ __launch_bounds__(1024) void k_wor_find(WorArgs A, int level) {
-    __shared__ uint32_t wsum[1024 / 64];
+// Pick the bin of this level that holds the rank-th key, from the level's
+// histogram g (1024 threads): update the rank, the chosen bins, and whether
+// the select is resolved.  Runs the domain checks first.
+__device__ void wor_pick(const WorArgs& A, int level, const uint32_t* g, uint32_t* wsum) {
     WorScalars* S = A.S;
     if (threadIdx.x == 0) {
         // domain checks once every candidate pass is complete
@@ -465,7 +468,6 @@ __global__ __launch_bounds__(1024) void k_wor_find(WorArgs A, int level) {
     }
     __syncthreads();
     if (S->status != WRS_OK || S->resolved) return;
-    const uint32_t* g = A.hist + (size_t)level * WOR_NB;
     constexpr int PER = WOR_NB / 1024;  // consecutive bins per thread
     const int t = threadIdx.x;
     uint32_t local = 0;
@@ -504,6 +506,41 @@ __global__ __launch_bounds__(1024) void k_wor_find(WorArgs A, int level) {
         } else {
             S->status = WRS_EDEVICE;  // more than WOR_SMALL keys equal at the boundary
         }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_wor_find(WorArgs A, int level) {
+    __shared__ uint32_t wsum[1024 / 64];
+    wor_pick(A, level, A.hist + (size_t)level * WOR_NB, wsum);
+}
+
+// The radix levels, all in one workgroup: each level counts the candidates
+// still in the set into an LDS histogram and picks its bin.  They are needed
+// only when the linear levels leave more than WOR_SMALL candidates in the
+// target bin (the fallback pass's candidate set, or keys piled into a tiny
+// range); otherwise the kernel finds the select resolved and exits, one
+// launch in place of a histogram and a pick per radix level.
+__global__ __launch_bounds__(1024) void k_wor_radix(WorArgs A) {
+    __shared__ uint32_t h[WOR_NB];
+    __shared__ uint32_t P[WOR_SHARDS + 1];
+    __shared__ uint32_t wsum[1024 / 64];
+    WorScalars* S = A.S;
+    for (int level = WOR_NLIN; level < WOR_NLEV; ++level) {
+        const uint32_t nc = wor_ncand(S);
+        const bool active = S->status == WRS_OK && !S->resolved && !S->bad && (int64_t)nc >= A.k;
+        if (active) {
+            load_cand_map(S, P);
+            for (int i = threadIdx.x; i < WOR_NB; i += 1024) h[i] = 0;
+            __syncthreads();
+            for (int64_t c = threadIdx.x; c < nc; c += 1024) {
+                const double key = A.ckey[cand_slot(P, A.scap, (uint32_t)c)];
+                if (wor_in_set(S, key, level)) atomicAdd(&h[wor_digit(key, level)], 1u);
+            }
+            __syncthreads();
+        }
+        wor_pick(A, level, h, wsum);  // runs the domain checks even when inactive
+        __syncthreads();
+        if (!active) return;
     }
 }
 
@@ -729,10 +766,11 @@ int launch_wor(const float* w, int64_t n, int64_t k, uint64_t seed, uint32_t sid
     hipLaunchKernelGGL(k_wor_shards, dim3(1), dim3(WOR_SHARDS), 0, st, A, 1);
     hipLaunchKernelGGL(k_wor_filter, dim3((unsigned)fblocks), dim3(WOR_TPB), 0, st, A, 2);
     hipLaunchKernelGGL(k_wor_shards, dim3(1), dim3(WOR_SHARDS), 0, st, A, 2);
-    for (int l = 0; l < WOR_NLEV; ++l) {
+    for (int l = 0; l < WOR_NLIN; ++l) {
         hipLaunchKernelGGL(k_wor_hist, dim3(cblocks), dim3(WOR_CAND_TPB), 0, st, A, l);
         hipLaunchKernelGGL(k_wor_find, dim3(1), dim3(1024), 0, st, A, l);
     }
+    hipLaunchKernelGGL(k_wor_radix, dim3(1), dim3(1024), 0, st, A);
     hipLaunchKernelGGL(k_wor_gather, dim3(cblocks), dim3(WOR_CAND_TPB), 0, st, A);
     hipLaunchKernelGGL(k_wor_final, dim3(1), dim3(1024), 0, st, A);
     hipLaunchKernelGGL(k_wor_mark, dim3(cblocks), dim3(WOR_CAND_TPB), 0, st, A);
