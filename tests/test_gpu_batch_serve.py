@@ -73,6 +73,40 @@ def test_batch_equals_single_calls(wrs, graph, fuse):
         wrs.batch_fuse_small(0)
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_fused_small_edges(wrs, graph):
+    """The fused small-table launch at its edges: n = 1, 2, the largest size it
+    takes (8192) and the next one (8193, which the phase launches take), k = 0
+    and draws far beyond n; every job equals its single calls."""
+    import torch
+    sizes = [1, 2, 3, 1023, 1024, 1025, 8191, 8192, 8193, 70000]
+    draws = [0, 1, 5, 100000]
+    jobs = []
+    for i, n in enumerate(sizes):
+        for j, k in enumerate(draws):
+            jobs.append(dict(n=n, kind="uniform" if (i + j) % 2 else "power", seed_w=1000 + 10 * i + j, k=k,
+                             stream_id=len(jobs)))
+    specs = make_batch(wrs, jobs)
+    for s in specs:
+        s["out"].fill_(-1)
+    arr = wrs.make_jobs(specs)
+    ws = torch.empty(wrs.batch_workspace_bytes(arr), dtype=torch.uint8, device="cuda:0")
+    wrs.batch_graph_mode(graph)
+    wrs.batch_fuse_small(wrs.FUSE_MAX_N)
+    say("fused small-table edges", len(jobs), "graph" if graph else "stream")
+    try:
+        wrs.batch_build_sample(arr, ws)
+        torch.cuda.synchronize()
+        assert all(st == wrs.OK for st in wrs.batch_status(ws, len(jobs)))
+    finally:
+        wrs.batch_graph_mode(True)
+        wrs.batch_fuse_small(0)
+    for i, s in enumerate(specs):
+        tab, smp = single(wrs, s["w"], s["n"], s["k"], 4, s["stream_id"])
+        assert np.array_equal(s["table"].cpu().numpy(), tab), i
+        assert np.array_equal(s["out"][:s["k"]].cpu().numpy(), smp), i
+
+
 def test_batch_graphs_share_a_workspace(wrs):
     """Two different batches alternate on one workspace: replaying the first
     batch's recorded graph must use its own descriptors again."""
