@@ -204,6 +204,16 @@ def main():
         tgbs = traffic / (samp_avg_ms * 1e-3) / 1e9
         result["roofline"]["traffic_gbs"] = round(tgbs, 1)
         result["roofline"]["traffic_frac"] = round(tgbs / HBM_PEAK_GBS, 4)
+    # the build's HBM bytes as the counters saw them (every kernel of one build,
+    # the larger of the two inputs' launches), against its average time
+    build_kernels = ("k_reduce", "k_finalize", "void k_tileagg<false>", "k_scan_seg", "k_scan_top", "k_scan_fix",
+                     "k_split", "void k_pack<false>")
+    counted = [load_traffic(kn) for kn in build_kernels]
+    if all(c is not None for c in counted):
+        cgbs = sum(counted) / (build_avg_ms * 1e-3) / 1e9
+        result["build_counted_traffic"] = {"bytes_per_build": int(sum(counted)), "gbs": round(cgbs, 1),
+                                           "frac": round(cgbs / HBM_PEAK_GBS, 4),
+                                           "algorithmic_bytes_per_build": int(build_bytes)}
     result["sampler_roofs"] = bench_roofs(torch, n, k, wrs.tune_get(wrs.TUNE_SAMPLE, k), samp_avg_ms)
     if not args.skip_extras:
         result["small"] = bench_small(wrs, torch, workloads, not args.no_tune)
