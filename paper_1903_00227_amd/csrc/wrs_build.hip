@@ -981,14 +981,17 @@ struct SideFetch {
     int cnt;        // items on this side
 };
 
-// side items [first, first + cnt) of the partitioned tile c
+// side items [first, first + cnt) of the partitioned tile c.  Every lane
+// loads each of the block-uniform k slots (a slot past cnt re-reads item
+// cnt - 1), so the loads write their registers unmasked and nothing waits for
+// them before the side is staged.
 template <bool LIST>
 __device__ __forceinline__ void fetch_side(const JobDesc& J, int64_t c, int first, int cnt, bool light,
                                            SideFetch& f) {
     f.cnt = cnt;
     f.base = 0;
     if (cnt == 0) return;
-    f.base = light ? glb(J.DP64)[c] : glb(J.EP64)[c];
+    f.base = (light ? glb(J.DP64) : glb(J.EP64))[c];
     const int k = uni((cnt + TPB - 1) / TPB);  // block-uniform: slots past it are skipped, not masked
     const int j0 = (int)threadIdx.x * k;
     const WRS_GLOBAL float* wp = glb(J.WP) + c * TILE + first;
@@ -997,11 +1000,9 @@ __device__ __forceinline__ void fetch_side(const JobDesc& J, int64_t c, int firs
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         if (e < k) {
-            const int j = j0 + e;
-            if (j < cnt) {
-                f.v[e] = wp[j];
-                if constexpr (LIST) f.o[e] = pi[j]; else f.o[e] = po[j];
-            }
+            const int j = min(j0 + e, cnt - 1);
+            f.v[e] = wp[j];
+            if constexpr (LIST) f.o[e] = pi[j]; else f.o[e] = po[j];
         }
     }
 }
@@ -1157,12 +1158,11 @@ __device__ __forceinline__ void pack_block(const JobDesc& J, int64_t lb, PackSha
         const bool need = s + 1 < s1;
         SideFetch fn;
         if (need) {
-            if (heavy_ev) {
-                const int hc = heavies_of(y + 1);
-                fetch_side<LIST>(J, y + 1, y + 1 < C ? tile_cnt(y + 1) - hc : 0, hc, false, fn);
-            } else {
-                fetch_side<LIST>(J, x + 1, 0, lights_of(x + 1), true, fn);
-            }
+            const int64_t cn = heavy_ev ? y + 1 : x + 1;
+            const int hc = heavies_of(y + 1);
+            const int cntn = heavy_ev ? hc : lights_of(x + 1);
+            const int firstn = (heavy_ev && y + 1 < C) ? tile_cnt(y + 1) - hc : 0;
+            fetch_side<LIST>(J, cn, firstn, cntn, !heavy_ev, fn);
         }
         const int64_t abase = x * TILE, bbase = y * TILE;
         int nlc, nhc;

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 TILE = 1024
+TPB = 256  # threads per pack block
 FH_NONE = -1
 
 
@@ -67,6 +68,12 @@ def run_block(rng, n, C, psteps, b, DP, EP, NL, PO):
         if cnt == 0:
             return []
         assert 0 <= c < C and 0 <= first and first + cnt <= tile_cnt(c)
+        # thread t loads slots t k .. t k + k - 1, each clamped to cnt - 1
+        k = -(-cnt // TPB)
+        for t in (0, TPB - 1):
+            for e in range(k):
+                j = min(t * k + e, cnt - 1)
+                assert 0 <= first + j < tile_cnt(c)
         return [c * TILE + PO[c][first + j] for j in range(cnt)]
 
     # the sides staged first, and the cursors inside them (any count the
@@ -86,8 +93,8 @@ def run_block(rng, n, C, psteps, b, DP, EP, NL, PO):
         assert has_h or has_l  # s < 2C: some tile event is left
         need = s + 1 < s1
         if need:
+            hc = heavies_of(y + 1)  # read on either kind of event, as the kernel does
             if heavy_ev:
-                hc = heavies_of(y + 1)
                 nxt = fetch(y + 1, tile_cnt(y + 1) - hc if y + 1 < C else 0, hc)
             else:
                 nxt = fetch(x + 1, 0, lights_of(x + 1))
