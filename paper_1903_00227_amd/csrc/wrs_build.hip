@@ -989,9 +989,8 @@ template <bool LIST>
 __device__ __forceinline__ void fetch_side(const JobDesc& J, int64_t c, int first, int cnt, bool light,
                                            SideFetch& f) {
     f.cnt = cnt;
-    f.base = 0;
+    f.base = 0;  // set from the window when the side is staged
     if (cnt == 0) return;
-    f.base = (light ? glb(J.DP64) : glb(J.EP64))[c];
     const int k = uni((cnt + TPB - 1) / TPB);  // block-uniform: slots past it are skipped, not masked
     const int j0 = (int)threadIdx.x * k;
     const WRS_GLOBAL float* wp = glb(J.WP) + c * TILE + first;
@@ -1112,6 +1111,8 @@ __device__ __forceinline__ void pack_block(const JobDesc& J, int64_t lb, PackSha
         const int hb = heavies_of(y0);
         fetch_side<LIST>(J, y0, y0 < C ? tile_cnt(y0) - hb : 0, hb, false, fb);
     }
+    fa.base = sh.dp[0];
+    fb.base = sh.ep[0];
     fill_side<true, LIST>(sh.A.key, sh.A.t, sh.A.id, fa, sc, n32, lscale, lres, sh.tmp);
     fill_side<false, LIST>(sh.B.key, (float*)nullptr, sh.B.id, fb, sc, n32, lscale, lres, sh.tmp);
     int nlx = fa.cnt, nhy = fb.cnt;
@@ -1234,6 +1235,7 @@ __device__ __forceinline__ void pack_block(const JobDesc& J, int64_t lb, PackSha
             ++y;
             ph = 0;
             if (need) {
+                fn.base = sh.ep[y - y0];
                 fill_side<false, LIST>(sh.B.key, (float*)nullptr, sh.B.id, fn, sc, n32, lscale, lres, sh.tmp);
                 nhy = fn.cnt;
             }
@@ -1241,6 +1243,7 @@ __device__ __forceinline__ void pack_block(const JobDesc& J, int64_t lb, PackSha
             ++x;
             pl = 0;
             if (need) {
+                fn.base = sh.dp[x - x0];
                 fill_side<true, LIST>(sh.A.key, sh.A.t, sh.A.id, fn, sc, n32, lscale, lres, sh.tmp);
                 nlx = fn.cnt;
             }

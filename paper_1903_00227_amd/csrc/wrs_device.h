@@ -123,14 +123,16 @@ __device__ __forceinline__ void dd_add(double& ah, double& al, double bh, double
 // and 31 carry the row totals forward.  A lane whose source lies outside its
 // row, or whose row is masked off, adds 0.
 // ---------------------------------------------------------------------------
-template <int CTRL, int ROW_MASK>
+// (BC: a row shift's source outside the row reads 0 by bound control, with no
+// identity in the destination first.)
+template <int CTRL, int ROW_MASK, bool BC = false>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t v, uint32_t identity = 0) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROW_MASK, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROW_MASK, 0xf, BC);
 }
-template <int CTRL, int ROW_MASK>
+template <int CTRL, int ROW_MASK, bool BC = false>
 __device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
-    const uint32_t lo = dpp_u32<CTRL, ROW_MASK>((uint32_t)v);
-    const uint32_t hi = dpp_u32<CTRL, ROW_MASK>((uint32_t)(v >> 32));
+    const uint32_t lo = dpp_u32<CTRL, ROW_MASK, BC>((uint32_t)v);
+    const uint32_t hi = dpp_u32<CTRL, ROW_MASK, BC>((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
 }
 constexpr int DPP_ROW_SHR = 0x110, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
@@ -146,10 +148,10 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 }
 
 __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
-    x += dpp_u64<DPP_ROW_SHR + 1, 0xf>(x);
-    x += dpp_u64<DPP_ROW_SHR + 2, 0xf>(x);
-    x += dpp_u64<DPP_ROW_SHR + 4, 0xf>(x);
-    x += dpp_u64<DPP_ROW_SHR + 8, 0xf>(x);
+    x += dpp_u64<DPP_ROW_SHR + 1, 0xf, true>(x);
+    x += dpp_u64<DPP_ROW_SHR + 2, 0xf, true>(x);
+    x += dpp_u64<DPP_ROW_SHR + 4, 0xf, true>(x);
+    x += dpp_u64<DPP_ROW_SHR + 8, 0xf, true>(x);
     x += dpp_u64<DPP_ROW_BCAST15, 0xa>(x);
     x += dpp_u64<DPP_ROW_BCAST31, 0xc>(x);
     return x;
