@@ -1025,10 +1025,18 @@ __device__ __forceinline__ void fill_side(uint64_t* key, float* tl, Id* id, cons
     for (int e = 0; e < IPT; ++e) {
         inc[e] = 0;
         if (e >= k) continue;
-        if (j0 + e < f.cnt) {
+        if constexpr (!LIST) {
+            // every lane computes the slot (a slot past the side holds a copy
+            // of its last item) and a slot past the side adds 0
+            const uint64_t z = size_keyunits(f.v[e], sc, n);
+            if constexpr (LIGHT) tv[e] = fminf(light_t(f.v[e], lscale), 1.0f);
+            const uint64_t d = LIGHT ? Qk - z : z - Qk;
+            inc[e] = (j0 + e < f.cnt) ? d : 0ull;
+            sum += inc[e];
+        } else if (j0 + e < f.cnt) {
             uint64_t z;
             float t = 0.0f;
-            if (LIST && is_residual_marker(__float_as_uint(f.v[e]))) {
+            if (is_residual_marker(__float_as_uint(f.v[e]))) {
                 const u128 m = glb(lres)[residual_slot(__float_as_uint(f.v[e]))];
                 const int ks = sc.kshift;
                 z = (uint64_t)(ks > 0 ? (m + ((u128)1 << (ks - 1))) >> ks : m);
@@ -1053,18 +1061,19 @@ __device__ __forceinline__ void fill_side(uint64_t* key, float* tl, Id* id, cons
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         if (e < k) {
+            // j < k TPB <= TILE: a slot past the side writes an entry that no
+            // search or output reads
             const int j = j0 + e;
-            if (j < f.cnt) {
-                if constexpr (LIGHT) {
-                    key[j] = acc;
-                    tl[j] = tv[e];
-                    acc += inc[e];
-                } else {
-                    acc += inc[e];
-                    key[j] = acc;
-                }
-                id[j] = (Id)f.o[e];
+            if (LIST && j >= f.cnt) continue;
+            if constexpr (LIGHT) {
+                key[j] = acc;
+                tl[j] = tv[e];
+                acc += inc[e];
+            } else {
+                acc += inc[e];
+                key[j] = acc;
             }
+            id[j] = (Id)f.o[e];
         }
     }
     __syncthreads();
