@@ -103,6 +103,7 @@ void build_ws_layout(JobDesc& J, void* ws, int64_t n, int32_t psteps) {
     J.sFH = (int32_t*)(b + L.sFH);
     J.lidx = nullptr;
     J.lres = nullptr;
+    J.lresf = nullptr;
     J.PI = nullptr;
     J.nmul = (uint32_t)n;
 }
@@ -144,7 +145,7 @@ size_t plus_ws_bytes(int64_t n) { return plus_offsets(n).total; }
 // 2-level workspace: the main job's scalars and reduction partials (the head of
 // its build layout), the top job's build workspace, then the meta-item lists.
 struct TwoOffsets {
-    size_t top, lidx, lw, lres, PI, total;
+    size_t top, lidx, lw, lres, lresf, PI, total;
 };
 
 static TwoOffsets two_offsets(int64_t n) {
@@ -156,6 +157,7 @@ static TwoOffsets two_offsets(int64_t n) {
     o.lidx = p; p = align256(p + sizeof(uint32_t) * Ct * TILE);
     o.lw = p;   p = align256(p + sizeof(float) * Ct * TILE);
     o.lres = p; p = align256(p + sizeof(u128) * G);
+    o.lresf = p; p = align256(p + sizeof(double) * G);
     o.PI = p;   p = align256(p + sizeof(uint32_t) * Ct * TILE);
     o.total = p;
     return o;
@@ -172,10 +174,12 @@ void twolevel_layout(void* ws, int64_t n, JobDesc& J, JobDesc& top, TwoLayout& T
     T.lidx = (uint32_t*)(b + o.lidx);
     T.lw = (float*)(b + o.lw);
     T.lres = (u128*)(b + o.lres);
+    T.lresf = (double*)(b + o.lresf);
     T.PI = (uint32_t*)(b + o.PI);
     top.w = T.lw;
     top.lidx = T.lidx;
     top.lres = T.lres;
+    top.lresf = T.lresf;
     top.PI = T.PI;
     top.nmul = (uint32_t)G;
     build_list_layout(top, G);
@@ -1010,11 +1014,12 @@ __device__ __forceinline__ void fetch_side(const JobDesc& J, int64_t c, int firs
 // Stage one side of a tile: keys are the tile's exact prefix plus the rounded
 // sizes of the side's items before (lights) or through (heavies) each item.
 // A light's t is computed here too.  List mode: a residual marker's size is
-// its exact n-scaled size from lres, rounded to key units.
+// its exact n-scaled size from lres, rounded to key units; a light marker's
+// threshold comes from lresf where that array holds its size.
 template <bool LIGHT, bool LIST, class Id>
 __device__ __forceinline__ void fill_side(uint64_t* key, float* tl, Id* id, const SideFetch& f,
                                           const BuildScalars& sc, uint32_t n, double lscale,
-                                          const u128* lres, uint64_t* tmp) {
+                                          const u128* lres, const double* lresf, uint64_t* tmp) {
     const int k = uni((f.cnt + TPB - 1) / TPB);  // block-uniform: slots past it are skipped, not masked
     const int j0 = (int)threadIdx.x * k;
     const uint64_t Qk = sc.Qk;
@@ -1037,10 +1042,14 @@ __device__ __forceinline__ void fill_side(uint64_t* key, float* tl, Id* id, cons
             uint64_t z;
             float t = 0.0f;
             if (is_residual_marker(__float_as_uint(f.v[e]))) {
-                const u128 m = glb(lres)[residual_slot(__float_as_uint(f.v[e]))];
+                const uint32_t slot = residual_slot(__float_as_uint(f.v[e]));
+                const u128 m = glb(lres)[slot];
                 const int ks = sc.kshift;
                 z = (uint64_t)(ks > 0 ? (m + ((u128)1 << (ks - 1))) >> ks : m);
-                if (LIGHT) t = (float)(u128_to_double(m) * sc.rQ);
+                if (LIGHT) {
+                    const double fs = lresf != nullptr ? glb(lresf)[slot] : -1.0;
+                    t = (float)((fs >= 0.0 ? fs : u128_to_double(m)) * sc.rQ);
+                }
             } else {
                 z = size_keyunits(f.v[e], sc, n);
                 if (LIGHT) t = light_t(f.v[e], lscale);
@@ -1090,6 +1099,7 @@ __device__ __forceinline__ void pack_block(const JobDesc& J, int64_t lb, PackSha
     const uint32_t n32 = J.nmul;
     const double lscale = sc.nscale * sc.rQ;
     const u128* lres = J.lres;
+    const double* lresf = J.lresf;
     const int64_t C = J.ntiles;
     const int psteps = J.psteps;  // PACK_STEPS_MIN..PACK_STEPS_MAX
     const int64_t s0 = lb * psteps;
@@ -1122,8 +1132,8 @@ __device__ __forceinline__ void pack_block(const JobDesc& J, int64_t lb, PackSha
     }
     fa.base = sh.dp[0];
     fb.base = sh.ep[0];
-    fill_side<true, LIST>(sh.A.key, sh.A.t, sh.A.id, fa, sc, n32, lscale, lres, sh.tmp);
-    fill_side<false, LIST>(sh.B.key, (float*)nullptr, sh.B.id, fb, sc, n32, lscale, lres, sh.tmp);
+    fill_side<true, LIST>(sh.A.key, sh.A.t, sh.A.id, fa, sc, n32, lscale, lres, lresf, sh.tmp);
+    fill_side<false, LIST>(sh.B.key, (float*)nullptr, sh.B.id, fb, sc, n32, lscale, lres, lresf, sh.tmp);
     int nlx = fa.cnt, nhy = fb.cnt;
     int64_t x = x0, y = y0;
     // DPkey(x) < v, with DPkey(C) = +infinity
@@ -1245,7 +1255,7 @@ __device__ __forceinline__ void pack_block(const JobDesc& J, int64_t lb, PackSha
             ph = 0;
             if (need) {
                 fn.base = sh.ep[y - y0];
-                fill_side<false, LIST>(sh.B.key, (float*)nullptr, sh.B.id, fn, sc, n32, lscale, lres, sh.tmp);
+                fill_side<false, LIST>(sh.B.key, (float*)nullptr, sh.B.id, fn, sc, n32, lscale, lres, lresf, sh.tmp);
                 nhy = fn.cnt;
             }
         } else {
@@ -1253,7 +1263,7 @@ __device__ __forceinline__ void pack_block(const JobDesc& J, int64_t lb, PackSha
             pl = 0;
             if (need) {
                 fn.base = sh.dp[x - x0];
-                fill_side<true, LIST>(sh.A.key, sh.A.t, sh.A.id, fn, sc, n32, lscale, lres, sh.tmp);
+                fill_side<true, LIST>(sh.A.key, sh.A.t, sh.A.id, fn, sc, n32, lscale, lres, lresf, sh.tmp);
                 nlx = fn.cnt;
             }
         }

@@ -286,7 +286,7 @@ __device__ __forceinline__ T* uni(T* p) {
 
 // Every field is copied: a field added to JobDesc or BuildScalars must be
 // added here too (the size checks catch a forgotten one).
-static_assert(sizeof(JobDesc) == 248, "job_uniform copies every JobDesc field");
+static_assert(sizeof(JobDesc) == 256, "job_uniform copies every JobDesc field");
 static_assert(sizeof(BuildScalars) == 128, "scalars_uniform copies every BuildScalars field");
 
 __device__ __forceinline__ JobDesc job_uniform(const JobDesc& J) {
@@ -323,6 +323,7 @@ __device__ __forceinline__ JobDesc job_uniform(const JobDesc& J) {
     u.sFH = uni(J.sFH);
     u.lidx = uni(J.lidx);
     u.lres = uni(J.lres);
+    u.lresf = uni(J.lresf);
     u.PI = uni(J.PI);
     u.nmul = uni(J.nmul);
     u.pad = 0;

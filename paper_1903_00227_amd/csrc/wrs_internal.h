@@ -83,6 +83,10 @@ struct JobDesc {
     // original item count.
     const uint32_t* lidx;
     const u128* lres;
+    // Optional, list mode: a marker's size as a double, for the light
+    // threshold of a marker whose lres entry is a rounded small number (a
+    // negative entry, or no array: the threshold comes from lres).
+    const double* lresf;
     uint32_t* PI;         // [C * TILE] list mode: original index of each WP item
     uint32_t nmul;        // n of the size scaling (= n outside list mode)
     int32_t pad;
@@ -143,6 +147,7 @@ struct TwoLayout {
     uint32_t* lidx;  // [C_top * TILE] list item g is meta-item g
     float* lw;       // [C_top * TILE] residual markers
     u128* lres;      // [G] exact G-scaled size of each meta-item
+    double* lresf;   // [G] the same size from the block's own grid, or -1
     uint32_t* PI;    // [C_top * TILE] list-mode partitioned indices
 };
 size_t twolevel_ws_bytes(int64_t n);

@@ -12,6 +12,11 @@
 // (G = number of blocks), which gives the top-level table over the blocks.
 // The top job keeps the items' grid (exponent and capacity Q), with only the
 // count-dependent scalars derived for G items, so those sizes are exact.
+// A block far lighter than the total (its sum below 2^40 units of that grid)
+// builds its own table on a finer grid of its own, set by its largest weight,
+// and gives the top level its size as a double for the meta-item's light
+// threshold: on the items' grid its sum would keep too few bits for a
+// relative error below 1e-6 (and be 0 for a block below the grid).
 // A query draws a block from the top table, then an item from the block's
 // table: the second level's table holds global indices, and the top table is
 // G entries (a few MB at most, resident in L2).
@@ -26,6 +31,7 @@ struct TwoShared {
     uint64_t d64[2][GTPB / 64];
     uint32_t d32[GTPB / 64];
     u128 d128[GTPB / 64];
+    int32_t emx[GTPB / 64];
 };
 
 __device__ __forceinline__ int bitlen_u128(u128 v) {
@@ -68,10 +74,41 @@ __global__ __launch_bounds__(GTPB) void k_twolvl(JobDesc J, TwoLayout T) {
     u128 S = 0;
 #pragma unroll
     for (int q = 0; q < GTPB / 64; ++q) S += sh.d128[q];
+    const u128 Sg = S;  // on the items' grid: the meta-item's size
+    // The grid of the block's own table: the items' grid, or for a block whose
+    // sum is below 2^40 units of it, the grid Gq = e - 226 set by the largest
+    // weight's biased exponent e, which puts every size below 2^100 and m S
+    // below 2^122 (a weight more than 2^76 below the largest is rounded on it).
+    int Gq = G;
+    if ((uint64_t)(Sg >> 64) == 0 && (uint64_t)Sg < (1ull << 40)) {  // the same for the whole block
+        int e = 0;
+#pragma unroll
+        for (int k = 0; k < GIPT; ++k) e = max(e, (int)(__float_as_uint(v[k]) >> 23));
+        const int we = -wave_incl_min(-e);  // lane 63: the wave's largest
+        if (lane == 63) sh.emx[wv] = we;
+        __syncthreads();  // also: every thread has read d128 above
+        int emax = 0;
+#pragma unroll
+        for (int q = 0; q < GTPB / 64; ++q) emax = max(emax, sh.emx[q]);
+        const int Gb = max(emax, 1) - 226;
+        if (Gb < G) {
+            Gq = Gb;
+            u128 s2 = 0;
+#pragma unroll
+            for (int k = 0; k < GIPT; ++k) s2 += quantize(v[k], Gb);
+            const u128 ws2 = wave_incl_scan(s2);
+            if (lane == 63) sh.d128[wv] = ws2;
+            __syncthreads();
+            S = 0;
+#pragma unroll
+            for (int q = 0; q < GTPB / 64; ++q) S += sh.d128[q];
+        }
+    }
     if (tid == 0) {  // the meta-item: a marker with its exact G-scaled size
         glb(T.lidx)[g] = g;
         glb(T.lw)[g] = __uint_as_float(residual_marker(g));
-        glb(T.lres)[g] = (u128)nblocks * S;
+        glb(T.lres)[g] = (u128)nblocks * Sg;
+        glb(T.lresf)[g] = Gq < G ? (double)nblocks * ldexp(u128_to_double(S), Gq - G) : -1.0;
     }
     if (S == 0) {  // a block of weight 0: every bucket keeps its item (never drawn)
 #pragma unroll
@@ -86,7 +123,7 @@ __global__ __launch_bounds__(GTPB) void k_twolvl(JobDesc J, TwoLayout T) {
     const uint64_t Qk = (uint64_t)((S + half) >> ks);
     const double Sd = u128_to_double(S);
     const double tscale = ldexp(1.0, ks) / Sd;
-    const double lscale = ldexp((double)m, -G) / Sd;
+    const double lscale = ldexp((double)m, -Gq) / Sd;
     uint32_t lbits = 0, hbits = 0;
     uint64_t z[GIPT];
     uint64_t sD = 0, sE = 0;
@@ -94,7 +131,7 @@ __global__ __launch_bounds__(GTPB) void k_twolvl(JobDesc J, TwoLayout T) {
 #pragma unroll
     for (int k = 0; k < GIPT; ++k) {
         const bool valid = i0 + k < m;
-        const u128 mq = (u128)(uint32_t)m * quantize(v[k], G);
+        const u128 mq = (u128)(uint32_t)m * quantize(v[k], Gq);
         const bool light = valid && mq <= S;
         const bool heavy = valid && !light;
         z[k] = (uint64_t)((mq + half) >> ks);

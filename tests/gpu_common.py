@@ -74,6 +74,12 @@ def family(name, n, seed):
         w = workloads.uniform(n, seed)
         w[rng.random(n) < 0.1] = np.float32(-0.0)
         return w
+    if name == "wide":
+        # binary exponents uniform in [-60, 60] (ratios up to 2^121: sizes below
+        # the quantization grid, wide tile sums), 5 % zeros
+        w = np.ldexp(1.0 + rng.random(n), rng.integers(-60, 61, n)).astype(np.float32)
+        w[rng.random(n) < 0.05] = 0.0
+        return w
     if name == "tiny_heavies":
         # many heavy items barely above the mean, a few very light items
         w = np.full(n, 1.0, np.float32)

@@ -41,7 +41,7 @@ def compare_sets(orc, w, k, seed, sid, got):
         assert np.all(np.abs(keys - kth) <= 1e-6 * kth), f"{diff.size} differing items away from the boundary"
 
 
-@pytest.mark.parametrize("fam", ["uniform", "power0.5", "power1", "ints", "equal", "dominant"])
+@pytest.mark.parametrize("fam", ["uniform", "power0.5", "power1", "ints", "equal", "dominant", "wide"])
 def test_wor_small(wrs, orc, fam):
     for n, k in [(1, 1), (10, 3), (1000, 1), (1000, 999), (5000, 100), (70000, 4096), (70000, 60000)]:
         w = family(fam, n, n + 3)
