@@ -74,6 +74,16 @@ def family(name, n, seed):
         w = workloads.uniform(n, seed)
         w[rng.random(n) < 0.1] = np.float32(-0.0)
         return w
+    if name == "ties":
+        # weights 1, 2 and 3 with as many 1s as 3s: the mean is exactly 2, every
+        # 2 sits on the light/heavy boundary, and the deficit and excess sums
+        # are integers that tie over and over in the merge
+        k = n // 3
+        w = np.full(n, 2.0, np.float32)
+        pos = rng.permutation(n)
+        w[pos[:k]] = 1.0
+        w[pos[k:2 * k]] = 3.0
+        return w
     if name == "wide":
         # binary exponents uniform in [-60, 60] (ratios up to 2^121: sizes below
         # the quantization grid, wide tile sums), 5 % zeros

@@ -26,7 +26,7 @@ def wrs():
 
 SIZES = [1, 2, 3, 5, 63, 1000, 1023, 1024, 1025, 2047, 4096, 5000, 3 * 1024 + 17, 40000, 65536, 65536 + 37]
 FAMILIES = ["uniform", "power0.5", "power1", "power2", "ints", "equal", "one", "dominant", "sorted_power1",
-            "tiny_heavies", "negzero", "wide"]
+            "tiny_heavies", "negzero", "wide", "ties"]
 
 
 @pytest.mark.parametrize("fam", FAMILIES)
@@ -51,7 +51,7 @@ def test_build_first_config(wrs, orc):
     check_against_sweep(orc, w, t, a)
 
 
-@pytest.mark.parametrize("fam", ["uniform", "power1", "wide"])
+@pytest.mark.parametrize("fam", ["uniform", "power1", "wide", "ties"])
 def test_build_2pow21(wrs, orc, fam):
     """Many tiles and pack blocks (2^21 items: 2048 tiles, 256 pack blocks)."""
     w = family(fam, 1 << 21, 9)

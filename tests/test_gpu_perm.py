@@ -61,7 +61,8 @@ def check_against_oracle(orc, w, seed, sid, p):
 
 
 SIZES = [1, 2, 63, 4095, 4096, 4097, 10000, 100003, (1 << 20) + 17]
-FAMILIES = ["uniform", "power0.5", "power1", "ints", "equal", "one", "negzero", "sorted_power1", "tiny_heavies"]
+FAMILIES = ["uniform", "power0.5", "power1", "ints", "equal", "one", "negzero", "sorted_power1", "tiny_heavies",
+            "wide", "ties"]
 
 
 @pytest.mark.parametrize("fam", FAMILIES)

@@ -33,7 +33,7 @@ def wrs():
 
 SIZES = [1, 2, 3, 63, 1000, 2047, 2048, 2049, 4096, 5000, 3 * 2048 + 17, 40000, 65536 + 37, 200001]
 FAMILIES = ["uniform", "power0.5", "power1", "power2", "ints", "equal", "one", "dominant", "sorted_power1",
-            "tiny_heavies", "negzero", "wide"]
+            "tiny_heavies", "negzero", "wide", "ties"]
 
 
 def check_against_psaplus(orc, w, t, a):
@@ -67,7 +67,7 @@ def test_build_plus_matches_oracle(wrs, orc, fam):
         check_against_psaplus(orc, w, t, a)
 
 
-@pytest.mark.parametrize("fam", ["uniform", "power1", "wide"])
+@pytest.mark.parametrize("fam", ["uniform", "power1", "wide", "ties"])
 def test_build_plus_2pow21(wrs, orc, fam):
     """1024 greedy blocks; on power-law input the splitting stage gets several
     hundred thousand items (many tiles and pack blocks)."""

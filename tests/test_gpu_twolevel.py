@@ -75,7 +75,7 @@ def check(orc, w, tt, at, t, a):
 
 SIZES = [1, 2, 2047, 2048, 2049, 5000, 3 * 2048 + 17, 40000, 200001, (1 << 20) + 5]
 FAMILIES = ["uniform", "power0.5", "power1", "power2", "ints", "equal", "one", "dominant", "sorted_power1",
-            "tiny_heavies", "negzero", "wide"]
+            "tiny_heavies", "negzero", "wide", "ties"]
 
 
 @pytest.mark.parametrize("fam", FAMILIES)
