@@ -17,7 +17,9 @@
 // (the caller's buffer is free again when the call returns) and from there
 // into pool memory on the batch's stream.
 #include <stdio.h>
+#include <stddef.h>
 #include <string.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <atomic>
@@ -328,16 +330,22 @@ static bool issue(Server& S) {
             phase_blocks(d[j], b);
             for (int p = 0; p < PH_COUNT; ++p) off[(size_t)p * (nb + 1) + j + 1] = off[(size_t)p * (nb + 1) + j] + b[p];
         }
-        char* h = S.staging[slot];
-        const size_t o_off = (sizeof(JobDesc) * nb + 255) & ~(size_t)255;
-        memcpy(h, d.data(), sizeof(JobDesc) * nb);
-        memcpy(h + o_off, off.data(), sizeof(int64_t) * off.size());
-        ok = hipMemcpyAsync(dev_desc, h, bb, hipMemcpyHostToDevice, st) == hipSuccess;
         JobTable jt;
         memset(&jt, 0, sizeof jt);
-        jt.jobs = (const JobDesc*)dev_desc;
-        jt.off = (const int64_t*)(dev_desc + o_off);
-        jt.njobs = nb;
+        if (nb == 1) {
+            // one build: its descriptor travels as the launches' argument, with
+            // no copy ahead of them
+            jt.one = d[0];
+        } else {
+            char* h = S.staging[slot];
+            const size_t o_off = (sizeof(JobDesc) * nb + 255) & ~(size_t)255;
+            memcpy(h, d.data(), sizeof(JobDesc) * nb);
+            memcpy(h + o_off, off.data(), sizeof(int64_t) * off.size());
+            ok = ok && hipMemcpyAsync(dev_desc, h, bb, hipMemcpyHostToDevice, st) == hipSuccess;
+            jt.jobs = (const JobDesc*)dev_desc;
+            jt.off = (const int64_t*)(dev_desc + o_off);
+            jt.njobs = nb;
+        }
         int64_t totals[PH_COUNT];
         for (int p = 0; p < PH_COUNT; ++p) totals[p] = off[(size_t)p * (nb + 1) + nb];
         ok = ok && launch_build(jt, totals, st) == hipSuccess;
@@ -351,8 +359,13 @@ static bool issue(Server& S) {
         // statuses for retire(): gathered on the device, one copy to the pinned buffer
         int32_t* d_st = (int32_t*)(dev_desc + bb + sb);
         int32_t* h_st = (int32_t*)(S.staging[slot] + bb + sb);
-        ok = ok && launch_collect_status(jt, d_st, st) == hipSuccess;
-        ok = ok && hipMemcpyAsync(h_st, d_st, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st) == hipSuccess;
+        if (nb == 1) {  // the status word is the first field of the job's scalars
+            const char* d_sc = (const char*)d[0].sc + offsetof(BuildScalars, status);
+            ok = ok && hipMemcpyAsync(h_st, d_sc, sizeof(int32_t), hipMemcpyDeviceToHost, st) == hipSuccess;
+        } else {
+            ok = ok && launch_collect_status(jt, d_st, st) == hipSuccess;
+            ok = ok && hipMemcpyAsync(h_st, d_st, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st) == hipSuccess;
+        }
     }
     if (ok && ns) {
         std::vector<JobDesc> d(ns);
@@ -369,16 +382,20 @@ static bool issue(Server& S) {
             d[j].sc = tb->sc;  // skips the draws if the build failed
             off[(size_t)PH_SAMPLE * (ns + 1) + j + 1] = off[(size_t)PH_SAMPLE * (ns + 1) + j] + sample_blocks(d[j]);
         }
-        char* h = S.staging[slot] + bb;
-        const size_t o_off = (sizeof(JobDesc) * ns + 255) & ~(size_t)255;
-        memcpy(h, d.data(), sizeof(JobDesc) * ns);
-        memcpy(h + o_off, off.data(), sizeof(int64_t) * off.size());
-        ok = ok && hipMemcpyAsync(dev_desc + bb, h, sb, hipMemcpyHostToDevice, st) == hipSuccess;
         JobTable jt;
         memset(&jt, 0, sizeof jt);
-        jt.jobs = (const JobDesc*)(dev_desc + bb);
-        jt.off = (const int64_t*)(dev_desc + bb + o_off);
-        jt.njobs = ns;
+        if (ns == 1) {
+            jt.one = d[0];  // one sample request: the descriptor is the launch's argument
+        } else {
+            char* h = S.staging[slot] + bb;
+            const size_t o_off = (sizeof(JobDesc) * ns + 255) & ~(size_t)255;
+            memcpy(h, d.data(), sizeof(JobDesc) * ns);
+            memcpy(h + o_off, off.data(), sizeof(int64_t) * off.size());
+            ok = ok && hipMemcpyAsync(dev_desc + bb, h, sb, hipMemcpyHostToDevice, st) == hipSuccess;
+            jt.jobs = (const JobDesc*)(dev_desc + bb);
+            jt.off = (const int64_t*)(dev_desc + bb + o_off);
+            jt.njobs = ns;
+        }
         ok = ok && launch_sample(jt, off[(size_t)PH_SAMPLE * (ns + 1) + ns], st) == hipSuccess;
         S.launches++;
     }
@@ -407,6 +424,9 @@ static bool issue(Server& S) {
 
 static void worker_main(Server* S) {
     (void)hipSetDevice(S->device);
+    // The completion poll below sleeps 5 us at a time; with the default 50 us
+    // timer slack of a thread each of those sleeps would last about 55 us.
+    (void)prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
     std::unique_lock<std::mutex> lk(S->mu);
     while (true) {
         retire(*S, false);
