@@ -422,16 +422,6 @@ static bool issue(Server& S) {
     return true;
 }
 
-// A submission issues what it can itself when the calling thread's device is
-// the server's (lock held): the worker would otherwise have to wake first.
-// Under load no slot is free and the worker batches the queue as before.
-static void issue_from_caller(Server& S) {
-    int d = -1;
-    if (hipGetDevice(&d) != hipSuccess || d != S.device) return;
-    while (issue(S)) {
-    }
-}
-
 static void worker_main(Server* S) {
     (void)hipSetDevice(S->device);
     // The completion poll below sleeps 5 us at a time; with the default 50 us
@@ -603,7 +593,6 @@ extern "C" int wrs_serve_submit_build(void* srv, const float* w, int64_t n, int3
     S->submitted++;
     S->builds++;
     S->items += (uint64_t)n;
-    issue_from_caller(*S);
     S->cv.notify_one();
     return WRS_OK;
 }
@@ -633,7 +622,6 @@ extern "C" int wrs_serve_submit_sample(void* srv, uint64_t table_id, int64_t k, 
     S->submitted++;
     S->samples++;
     S->drawn += (uint64_t)k;
-    issue_from_caller(*S);
     S->cv.notify_one();
     return WRS_OK;
 }
