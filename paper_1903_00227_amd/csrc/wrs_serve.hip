@@ -26,6 +26,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -80,7 +81,8 @@ struct Table {
     int refs = 0;                // queued or running requests using the table
     int status = WRS_OK;
     BuildScalars* sc = nullptr;  // status word of the build (pool memory)
-    uint64_t last_use = 0;
+    bool idle = false;           // in the server's idle list
+    std::list<Table*>::iterator idle_at;
 };
 
 struct Request {
@@ -114,12 +116,15 @@ struct Server {
     Pool pool;
     char* h_arena = nullptr;     // pinned staging for host weights (cfg.host_stage_bytes)
     FirstFit stage;
-    std::vector<hipEvent_t> free_events;  // recycled submission events
+    std::vector<hipEvent_t> free_events;  // recycled events (submissions, batches, tables)
     std::mutex mu;
     std::condition_variable cv, cv_done;
     std::deque<Request*> queue;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     std::unordered_map<uint64_t, std::unique_ptr<Table>> tables;
+    // Tables that may be evicted (built or failed, no request pending), least
+    // recently used first: an eviction takes the front, with no scan.
+    std::list<Table*> idle;
     std::vector<hipStream_t> streams;
     std::vector<char*> staging;   // pinned host buffers for descriptors, one per slot
     std::vector<char*> dev_desc;  // device descriptor buffers (pool memory), one per slot
@@ -130,7 +135,6 @@ struct Server {
     std::thread worker;
     bool stop = false;
     uint64_t next_id = 1;
-    uint64_t clock = 0;
     // statistics
     uint64_t submitted = 0, completed = 0, failed = 0, builds = 0, samples = 0, items = 0, drawn = 0, launches = 0;
     double t_first = -1, t_last = 0;
@@ -150,6 +154,29 @@ static size_t status_bytes(int njobs) { return ((size_t)sizeof(int32_t) * njobs 
 // build and sample job tables (nb + ns <= maxb) and the build statuses.
 static size_t slot_bytes(int maxb) { return 2 * descriptor_bytes(maxb) + status_bytes(maxb); }
 
+// Idle-list membership follows the table's state (lock held): in the list
+// exactly when its build is over and no request uses it.
+static void idle_update(Server& S, Table* t) {
+    const bool want = t->refs == 0 && (t->state == T_READY || t->state == T_FAILED);
+    if (want && !t->idle) {
+        t->idle_at = S.idle.insert(S.idle.end(), t);
+        t->idle = true;
+    } else if (!want && t->idle) {
+        S.idle.erase(t->idle_at);
+        t->idle = false;
+    }
+}
+
+// An event from the recycled ones, or a new one (lock held).
+static hipError_t take_event(Server& S, hipEvent_t* e) {
+    if (!S.free_events.empty()) {
+        *e = S.free_events.back();
+        S.free_events.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreateWithFlags(e, hipEventDisableTiming);
+}
+
 // A request is finished once its batch has run, or when it fails before it
 // is issued: the event it waited for, and the host copy of its weights, are
 // free again.
@@ -166,7 +193,10 @@ static void finish_request(Server& S, Request* r, int status, double t) {
     S.lat_us.push_back((t - r->t_submit) * 1e6);
     S.t_last = std::max(S.t_last, t);
     auto it = S.tables.find(r->table_id);
-    if (it != S.tables.end()) it->second->refs--;
+    if (it != S.tables.end()) {
+        it->second->refs--;
+        idle_update(S, it->second.get());
+    }
     S.cv_done.notify_all();
 }
 
@@ -192,7 +222,7 @@ static void retire(Server& S, bool block) {
             finish_request(S, r, st, t);
         }
         for (auto& p : b.scratch) S.pool.release(p.first, p.second);
-        if (b.ev) (void)hipEventDestroy(b.ev);
+        if (b.ev) S.free_events.push_back(b.ev);  // complete: reused by a later batch
         S.slot_busy[b.slot] = false;
         S.running.pop_front();
         S.cv_done.notify_all();
@@ -201,17 +231,13 @@ static void retire(Server& S, bool block) {
 
 // Drop the least recently used idle table (lock held); false if none is idle.
 static bool evict_lru(Server& S) {
-    Table* victim = nullptr;
-    for (auto& kv : S.tables) {
-        Table* t = kv.second.get();
-        if (t->refs == 0 && (t->state == T_READY || t->state == T_FAILED) &&
-            (!victim || t->last_use < victim->last_use))
-            victim = t;
-    }
-    if (!victim) return false;
+    if (S.idle.empty()) return false;
+    Table* victim = S.idle.front();
+    S.idle.pop_front();
+    victim->idle = false;
     S.pool.release(victim->d_table, victim->table_bytes);
     S.pool.release(victim->sc, 256);
-    if (victim->ready) (void)hipEventDestroy(victim->ready);
+    if (victim->ready) S.free_events.push_back(victim->ready);  // its build finished
     S.tables.erase(victim->id);
     return true;
 }
@@ -283,7 +309,6 @@ static bool issue(Server& S) {
             }
             smp.push_back(r);
         }
-        tb->last_use = ++S.clock;
         take.push_back(r);
         S.queue.pop_front();
     }
@@ -352,8 +377,8 @@ static bool issue(Server& S) {
         S.launches++;
         for (int j = 0; j < nb; ++j) {
             Table* tb = S.tables[bld[j]->table_id].get();
-            if (!tb->ready) (void)hipEventCreateWithFlags(&tb->ready, hipEventDisableTiming);
-            (void)hipEventRecord(tb->ready, st);
+            if (!tb->ready) (void)take_event(S, &tb->ready);
+            if (tb->ready) (void)hipEventRecord(tb->ready, st);
             bld[j]->build_index = j;
         }
         // statuses for retire(): gathered on the device, one copy to the pinned buffer
@@ -404,7 +429,7 @@ static bool issue(Server& S) {
     b.reqs = take;
     b.scratch = scratch;
     b.h_status = (ok && nb) ? (const int32_t*)(S.staging[slot] + bb + sb) : nullptr;
-    if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+    if (take_event(S, &b.ev) != hipSuccess) {
         b.ev = nullptr;
         ok = false;
     } else if (hipEventRecord(b.ev, st) != hipSuccess) {
@@ -608,6 +633,7 @@ extern "C" int wrs_serve_submit_sample(void* srv, uint64_t table_id, int64_t k, 
     const int er = submission_event(*S, stream, &r->after);
     if (er != WRS_OK) return er;
     it->second->refs++;
+    idle_update(*S, it->second.get());
     r->id = S->next_id++;
     r->op = OP_SAMPLE;
     r->table_id = table_id;
@@ -669,9 +695,13 @@ extern "C" int wrs_serve_release_table(void* srv, uint64_t table_id) {
     if (it == S->tables.end()) return WRS_ENOTFOUND;
     Table* t = it->second.get();
     if (t->refs > 0 || t->state == T_QUEUED || t->state == T_BUILDING) return WRS_EBUSY;
+    if (t->idle) {
+        S->idle.erase(t->idle_at);
+        t->idle = false;
+    }
     S->pool.release(t->d_table, t->table_bytes);
     S->pool.release(t->sc, 256);
-    if (t->ready) (void)hipEventDestroy(t->ready);
+    if (t->ready) S->free_events.push_back(t->ready);
     S->tables.erase(it);
     return WRS_OK;
 }
