@@ -4,7 +4,10 @@
 // this allocator: sizes round up to 256 bytes, a request takes the free range
 // with the lowest offset that holds it, and a released range merges with free
 // neighbours.  It never touches the memory it manages, so it can be exercised
-// on any address range.
+// on any address range.  The lengths of the free ranges are kept in a sorted
+// multiset beside them, so a request that no range holds fails at once
+// instead of scanning every range (a server retrying after evictions makes
+// many such requests when the budget is fragmented).
 #ifndef WRS_POOL_H
 #define WRS_POOL_H
 
@@ -13,6 +16,7 @@
 #include <algorithm>
 #include <iterator>
 #include <map>
+#include <set>
 
 namespace wrs {
 
@@ -24,15 +28,17 @@ class FirstFit {
         size_ = bytes & ~(size_t)255;
         used_ = peak_ = 0;
         free_.clear();
-        if (size_) free_[0] = size_;
+        lens_.clear();
+        if (size_) put(0, size_);
     }
     void* alloc(size_t bytes) {
         bytes = round(bytes);
+        if (lens_.empty() || *lens_.rbegin() < bytes) return nullptr;  // no range holds it
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second >= bytes) {
                 const size_t off = it->first, sz = it->second;
-                free_.erase(it);
-                if (sz > bytes) free_[off + bytes] = sz - bytes;
+                take(it);
+                if (sz > bytes) put(off + bytes, sz - bytes);
                 used_ += bytes;
                 peak_ = std::max(peak_, used_);
                 return base_ + off;
@@ -49,16 +55,18 @@ class FirstFit {
         auto nx = free_.lower_bound(off);
         if (nx != free_.end() && off + bytes == nx->first) {
             bytes += nx->second;
-            nx = free_.erase(nx);
+            nx = take(nx);
         }
         if (nx != free_.begin()) {
             auto pv = std::prev(nx);
             if (pv->first + pv->second == off) {
-                pv->second += bytes;
+                const size_t at = pv->first, len = pv->second + bytes;
+                take(pv);
+                put(at, len);
                 return;
             }
         }
-        free_[off] = bytes;
+        put(off, bytes);
     }
     size_t used() const { return used_; }
     size_t peak() const { return peak_; }
@@ -68,9 +76,19 @@ class FirstFit {
 
    private:
     static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
+    // free range [off, off + len) in, or out, of both indexes
+    void put(size_t off, size_t len) {
+        free_[off] = len;
+        lens_.insert(len);
+    }
+    std::map<size_t, size_t>::iterator take(std::map<size_t, size_t>::iterator it) {
+        lens_.erase(lens_.find(it->second));
+        return free_.erase(it);
+    }
     char* base_ = nullptr;
     size_t size_ = 0, used_ = 0, peak_ = 0;
     std::map<size_t, size_t> free_;  // offset -> length of each free range
+    std::multiset<size_t> lens_;     // the lengths of those ranges
 };
 
 }  // namespace wrs
