@@ -377,8 +377,9 @@ static bool issue(Server& S) {
         S.launches++;
         for (int j = 0; j < nb; ++j) {
             Table* tb = S.tables[bld[j]->table_id].get();
-            if (!tb->ready) (void)take_event(S, &tb->ready);
-            if (tb->ready) (void)hipEventRecord(tb->ready, st);
+            // samples in other batches wait for this event: without it the batch fails
+            if (!tb->ready && take_event(S, &tb->ready) != hipSuccess) tb->ready = nullptr;
+            ok = ok && tb->ready != nullptr && hipEventRecord(tb->ready, st) == hipSuccess;
             bld[j]->build_index = j;
         }
         // statuses for retire(): gathered on the device, one copy to the pinned buffer
