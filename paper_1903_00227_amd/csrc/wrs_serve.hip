@@ -77,7 +77,7 @@ struct Table {
     wrs_entry* d_table = nullptr;
     size_t table_bytes = 0;
     TableState state = T_QUEUED;
-    hipEvent_t ready = nullptr;  // recorded after the build launch
+    hipEvent_t ready = nullptr;  // while it builds: the event of its batch (not owned)
     int refs = 0;                // queued or running requests using the table
     int status = WRS_OK;
     BuildScalars* sc = nullptr;  // status word of the build (pool memory)
@@ -217,6 +217,7 @@ static void retire(Server& S, bool block) {
                 if (st == WRS_OK) st = b.h_status ? b.h_status[r->build_index] : WRS_EDEVICE;
                 tb->state = (st == WRS_OK) ? T_READY : T_FAILED;
                 tb->status = st;
+                tb->ready = nullptr;  // the batch's event is recycled below
             }
             if (r->op == OP_SAMPLE && tb && tb->status != WRS_OK) st = tb->status;
             finish_request(S, r, st, t);
@@ -237,7 +238,6 @@ static bool evict_lru(Server& S) {
     victim->idle = false;
     S.pool.release(victim->d_table, victim->table_bytes);
     S.pool.release(victim->sc, 256);
-    if (victim->ready) S.free_events.push_back(victim->ready);  // its build finished
     S.tables.erase(victim->id);
     return true;
 }
@@ -375,13 +375,7 @@ static bool issue(Server& S) {
         for (int p = 0; p < PH_COUNT; ++p) totals[p] = off[(size_t)p * (nb + 1) + nb];
         ok = ok && launch_build(jt, totals, st) == hipSuccess;
         S.launches++;
-        for (int j = 0; j < nb; ++j) {
-            Table* tb = S.tables[bld[j]->table_id].get();
-            // samples in other batches wait for this event: without it the batch fails
-            if (!tb->ready && take_event(S, &tb->ready) != hipSuccess) tb->ready = nullptr;
-            ok = ok && tb->ready != nullptr && hipEventRecord(tb->ready, st) == hipSuccess;
-            bld[j]->build_index = j;
-        }
+        for (int j = 0; j < nb; ++j) bld[j]->build_index = j;
         // statuses for retire(): gathered on the device, one copy to the pinned buffer
         int32_t* d_st = (int32_t*)(dev_desc + bb + sb);
         int32_t* h_st = (int32_t*)(S.staging[slot] + bb + sb);
@@ -436,6 +430,10 @@ static bool issue(Server& S) {
     } else if (hipEventRecord(b.ev, st) != hipSuccess) {
         ok = false;
     }
+    // A sample issued later, in another batch, of a table this batch builds
+    // waits for this event (recorded after all of the batch's launches, one
+    // event per batch instead of one per build).
+    for (Request* r : bld) S.tables[r->table_id]->ready = b.ev;
     b.ok = ok;
     if (!ok) {
         // retire() fails every request of the batch; wait so that its slot
@@ -702,7 +700,6 @@ extern "C" int wrs_serve_release_table(void* srv, uint64_t table_id) {
     }
     S->pool.release(t->d_table, t->table_bytes);
     S->pool.release(t->sc, 256);
-    if (t->ready) S->free_events.push_back(t->ready);
     S->tables.erase(it);
     return WRS_OK;
 }
@@ -762,8 +759,6 @@ extern "C" int wrs_serve_destroy(void* srv) {
         S->cv_done.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
-    for (auto& kv : S->tables)
-        if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
     release_slots(S);
     delete S;
     return WRS_OK;
