@@ -525,7 +525,7 @@ def bench_batched(wrs, torch, np, workloads, run_tune=True):
             "fused_hbm_frac_28B_per_item": round(28.0 * items / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def bench_served(wrs, torch, np, workloads, count=20000, warmup=1000, repeats=3, inflight=2,
+def bench_served(wrs, torch, np, workloads, count=20000, warmup=1000, repeats=3, inflight=4,
                  lambdas=(0.25, 0.5, 0.75, 0.9, 1.1)):
     """Poisson request stream (seed 5): `warmup` requests, then `count`
     measured ones, at rates lambda x the one-at-a-time capacity (the
