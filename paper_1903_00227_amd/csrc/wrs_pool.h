@@ -72,6 +72,12 @@ class FirstFit {
     size_t peak() const { return peak_; }
     size_t size() const { return size_; }
     size_t free_ranges() const { return free_.size(); }
+    // The length index holds exactly the free ranges' lengths (a check for tests).
+    bool index_consistent() const {
+        std::multiset<size_t> l;
+        for (const auto& kv : free_) l.insert(kv.second);
+        return l == lens_;
+    }
     void* base() const { return base_; }
 
    private:

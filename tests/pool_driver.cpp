@@ -1,7 +1,7 @@
 // Test driver (host code, CPU only): runs the request server's first-fit
 // allocator over an address range it never dereferences.  Reads commands from
 // stdin -- "a BYTES" (allocate; prints the offset or -1), "r OFFSET BYTES"
-// (release) -- and prints "used PEAK_USED RANGES" at the end.
+// (release) -- and prints "USED PEAK_USED RANGES SIZE INDEX_OK" at the end.
 #include <stdio.h>
 
 #include "wrs_pool.h"
@@ -28,6 +28,6 @@ int main() {
             return 2;
         }
     }
-    printf("%zu %zu %zu %zu\n", ff.used(), ff.peak(), ff.free_ranges(), ff.size());
+    printf("%zu %zu %zu %zu %d\n", ff.used(), ff.peak(), ff.free_ranges(), ff.size(), ff.index_consistent() ? 1 : 0);
     return 0;
 }

@@ -1,7 +1,8 @@
 """The request server's HBM-budget allocator (host code, CPU only), compiled
 with g++ into a small driver and compared with a plain first-fit model over a
 list of free ranges: the same offsets for every request, the same bytes in
-use and peak, and free neighbours merged back into a single range."""
+use and peak, free neighbours merged back into a single range, and the
+allocator's index of free lengths equal to its free ranges after every run."""
 import os
 import random
 import shutil
@@ -68,7 +69,8 @@ def run(exe, size, ops):
     lines = r.stdout.split("\n")
     nalloc = sum(1 for o in ops if o[0] == "a")
     offs = [int(x) for x in lines[:nalloc]]
-    used, peak, ranges, sz = (int(x) for x in lines[nalloc].split())
+    used, peak, ranges, sz, index_ok = (int(x) for x in lines[nalloc].split())
+    assert index_ok == 1  # the length index matches the free ranges
     return offs, used, peak, ranges, sz
 
 
