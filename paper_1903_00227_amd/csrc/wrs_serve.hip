@@ -134,6 +134,7 @@ struct Server {
     std::deque<Batch> running;
     std::thread worker;
     bool stop = false;
+    std::atomic<uint64_t> arrivals{0};  // submissions, readable without the lock
     uint64_t next_id = 1;
     // statistics
     uint64_t submitted = 0, completed = 0, failed = 0, builds = 0, samples = 0, items = 0, drawn = 0, launches = 0;
@@ -459,7 +460,16 @@ static void worker_main(Server* S) {
         if (S->stop && S->queue.empty() && S->running.empty()) break;
         if (!issued) {
             if (S->running.empty()) {
-                S->cv.wait_for(lk, std::chrono::milliseconds(50));
+                // Idle: watch for a submission for up to 200 us before sleeping
+                // on the condition variable, so that a request arriving soon is
+                // issued without the wake-up of a sleeping thread.
+                const uint64_t seen = S->arrivals.load(std::memory_order_acquire);
+                lk.unlock();
+                bool arrived = false;
+                for (const double t0 = now_s(); !arrived && now_s() - t0 < 200e-6;)
+                    arrived = S->arrivals.load(std::memory_order_acquire) != seen;
+                lk.lock();
+                if (!arrived && S->queue.empty() && !S->stop) S->cv.wait_for(lk, std::chrono::milliseconds(50));
             } else {
                 // poll the oldest batch; short sleeps keep the completion times sharp
                 lk.unlock();
@@ -615,6 +625,7 @@ extern "C" int wrs_serve_submit_build(void* srv, const float* w, int64_t n, int3
     S->tables[t->id] = std::move(t);
     S->reqs[r->id] = std::move(r);
     S->submitted++;
+    S->arrivals.fetch_add(1, std::memory_order_release);
     S->builds++;
     S->items += (uint64_t)n;
     S->cv.notify_one();
@@ -645,6 +656,7 @@ extern "C" int wrs_serve_submit_sample(void* srv, uint64_t table_id, int64_t k, 
     S->queue.push_back(r.get());
     S->reqs[r->id] = std::move(r);
     S->submitted++;
+    S->arrivals.fetch_add(1, std::memory_order_release);
     S->samples++;
     S->drawn += (uint64_t)k;
     S->cv.notify_one();
