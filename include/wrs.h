@@ -188,7 +188,11 @@ int wrs_os_sample(const void* d_os, int64_t n, int64_t k, uint64_t seed, int32_t
  * block as the instance; aliases are global item indices), and
  * d_top[0..G), G = ceil(n / WRS_TWOLEVEL_BLOCK), the alias table over the
  * meta-items (the splitting construction of wrs_alias_build).  A block of
- * total weight 0 keeps t = 1, alias = self and is never drawn.  d_w: n FP32
+ * total weight 0 keeps t = 1, alias = self and is never drawn.  A block far
+ * lighter than the total (its sum below 2^40 units of the items' grid) builds
+ * its table on a grid of its own and gives its meta-item a light threshold
+ * from its size as a double, so every positive weight keeps its probability
+ * within 1e-6 relative.  d_w: n FP32
  * weights (device).  d_table, d_top: device, 8-byte aligned.  d_ws:
  * wrs_workspace_bytes(WRS_OP_TWOLEVEL, n, 0) bytes (device, 256-byte aligned,
  * about 0.1 byte per item plus a fixed part).  Stream-ordered, no host wait
